@@ -1,0 +1,118 @@
+"""Seeded synthetic image cubes (input generator shared by tests and benchmark).
+
+This module synthesises inputs only; it holds none of the search's arithmetic.
+Cubes are laid out [t][s][p] (time, sub-band, pixel with p = y*nx + x) and
+drawn from NumPy's PCG64 generator so that every run with the same seed sees
+identical bytes.
+
+Workloads follow the paper's shapes and value distributions: Gaussian image
+noise with a per-pixel sigma, boxcar-shaped dispersed pulses (the injection
+tests of sections 3.1 and 3.2), broadband zero-DM spikes and narrowband
+sub-band stripes (the RFI classes of section 4.3 and appendix B). No survey
+data are used; none are available.
+
+Sky model: a pulse of DM `dm` that starts at sample t0 at the reference
+(highest) frequency arrives in sub-band s at t0 + round(k*dm*(f_s^-2 -
+f_ref^-2)/dt) -- the cold-plasma dispersion law, rounded to whole samples as
+the synthetic workload prescribes.
+"""
+import numpy as np
+
+
+def noise_cube(nt, ns, npix, seed, sigma_pix=None, dtype=np.float32):
+    """Gaussian noise [t][s][p]; sigma per pixel (default 1)."""
+    rng = np.random.default_rng(seed)
+    cube = rng.standard_normal((nt, ns, npix), dtype=np.float32)
+    if sigma_pix is not None:
+        cube *= np.asarray(sigma_pix, dtype=np.float32)[None, None, :]
+    return cube.astype(dtype, copy=False)
+
+
+def arrival_offsets(dm, freqs_ghz, f_ref_ghz, dt_ms, k_dm_ms=4.15):
+    """Sky model: per-sub-band arrival offset (samples) of a pulse of this DM."""
+    f = np.asarray(freqs_ghz, dtype=np.float64)
+    secs = k_dm_ms * float(dm) * (f ** -2.0 - float(f_ref_ghz) ** -2.0)
+    return np.rint(secs / float(dt_ms)).astype(np.int64)
+
+
+def inject_boxcar(cube, p, t0, offsets, width, amp):
+    """Add `amp` to samples t0+offsets[s] .. +width-1 of every sub-band at pixel p."""
+    nt, ns, _ = cube.shape
+    for s in range(ns):
+        a = int(t0) + int(offsets[s])
+        lo, hi = max(a, 0), min(a + int(width), nt)
+        if hi > lo:
+            cube[lo:hi, s, p] += np.asarray(amp, dtype=cube.dtype)
+
+
+def zero_dm_spike(cube, t, amp_pix):
+    """Broadband single-sample spike at sample t in every pixel and sub-band."""
+    cube[t, :, :] += np.asarray(amp_pix, dtype=cube.dtype)[None, :]
+
+
+def stripe(cube, s, amp_pix, t_lo=0, t_hi=None):
+    """Narrowband stripe: sub-band s raised over [t_lo, t_hi) in every pixel."""
+    t_hi = cube.shape[0] if t_hi is None else t_hi
+    cube[t_lo:t_hi, s, :] += np.asarray(amp_pix, dtype=cube.dtype)[None, :]
+
+
+# ---------------------------------------------------------------- configs
+C1_FREQS = np.linspace(1.311, 1.499, 4)
+C2_FREQS = np.linspace(1.311, 1.499, 16)
+DT_MS = 134.2
+
+
+def widths_pow2(max_pow2, extra=()):
+    return [1 << i for i in range(max_pow2.bit_length()) if (1 << i) <= max_pow2] + list(extra)
+
+
+def config1(seed=0, amp=1.0, t0=20, width=4, dm=500.0, pixel=(16, 16)):
+    """Tiny FP32 search: 32x32 px, 4 sub-bands, 64 samples, one injected pulse."""
+    nx = ny = 32
+    cube = noise_cube(64, 4, nx * ny, seed)
+    p = pixel[1] * nx + pixel[0]
+    off = arrival_offsets(dm, C1_FREQS, C1_FREQS.max(), DT_MS)
+    inject_boxcar(cube, p, t0, off, width, amp)
+    meta = dict(nx=nx, ny=ny, freqs=C1_FREQS, f_ref=float(C1_FREQS.max()), dt_ms=DT_MS,
+                dms=np.linspace(0.0, 1000.0, 8), widths=[1, 2, 4, 8, 16], theta=6.0,
+                injections=[dict(p=p, t0=t0, dm=dm, width=width, amp=amp, offsets=off)])
+    return cube, meta
+
+
+def config2(seed=2, nx=256, ny=256, nt=2048, ns=16, n_pulses=100, n_spikes=20,
+            n_stripes=2, rfi_sigma=5.0, n_dm=32, dm_max=4000.0):
+    """Survey-shape search: 256x256 px, 16 sub-bands, 2048 samples, pulses and RFI.
+
+    sigma_p ~ U(0.8, 1.2) per pixel; pulses at distinct random pixels with
+    DM ~ U(0, dm_max), width = round(exp U(0, ln 1200)), S/N ~ U(6, 50) and
+    amplitude S/N * sigma_p / sqrt(width * n_sub); zero-DM spikes of 5 sigma_p
+    per sub-band; full-duration sub-band stripes of 5 sigma_p.
+    """
+    freqs = np.linspace(1.311, 1.499, ns)
+    f_ref = float(freqs.max())
+    npix = nx * ny
+    rng = np.random.default_rng(seed + 1_000_003)
+    sig = rng.uniform(0.8, 1.2, npix).astype(np.float32)
+    cube = noise_cube(nt, ns, npix, seed, sig)
+    pix = rng.choice(npix, size=n_pulses, replace=False)
+    inj = []
+    for p in pix:
+        dm = rng.uniform(0.0, dm_max)
+        w = int(np.rint(np.exp(rng.uniform(0.0, np.log(1200.0)))))
+        snr = rng.uniform(6.0, 50.0)
+        off = arrival_offsets(dm, freqs, f_ref, DT_MS)
+        t_hi = nt - int(off.max()) - w
+        t0 = int(rng.integers(0, max(t_hi, 0) + 1))
+        amp = snr * float(sig[p]) / np.sqrt(w * ns)
+        inject_boxcar(cube, int(p), t0, off, w, amp)
+        inj.append(dict(p=int(p), t0=t0, dm=dm, width=w, snr=snr, amp=amp, offsets=off))
+    spikes = rng.choice(nt, size=n_spikes, replace=False)
+    for t in spikes:
+        zero_dm_spike(cube, int(t), rfi_sigma * sig)
+    stripes = rng.choice(ns, size=n_stripes, replace=False)
+    for s in stripes:
+        stripe(cube, int(s), rfi_sigma * sig)
+    meta = dict(nx=nx, ny=ny, freqs=freqs, f_ref=f_ref, dt_ms=DT_MS,
+                dms=np.linspace(0.0, dm_max, n_dm), widths=widths_pow2(1024, (1200,)),
+                theta=6.0, sigma_pix=sig, injections=inj, spikes=spikes, stripes=stripes)
+    return cube, meta
