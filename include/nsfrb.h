@@ -1,0 +1,159 @@
+/*
+ * nsfrb.h -- C ABI of the MI355X (gfx950) image-plane single-pulse search.
+ *
+ * The library implements the search of section 2.2 of arXiv:2510.18136 (the
+ * `cerberus` pipeline of the DSA-110 NSFRB system) on one GPU:
+ *   1. robust noise statistics per (pixel, sub-band): FP64 median and MAD,
+ *      sigma = 1.482602218505602 * MAD                    (section 2.2; 3.2)
+ *   2. normalise z = (x - median) / sigma in FP64, round to FP32 and then to
+ *      the store dtype, written in the search layout    (section 2.2)
+ *   3. incoherent de-dispersion with a precomputed integer shift table,
+ *      delta[d][s] = rint(k_dm * DM_d * (f_s^-2 - f_ref^-2) / dt)
+ *                                                       (section 2.2, t_BW law)
+ *   4. boxcar sums over a list of widths, S/N = sum / sqrt(n_sub * w)
+ *   5. maximum S/N over time and its time of arrival for every
+ *      (DM, width, pixel)                               (sections 2.2, 2.3)
+ *   6. per-pixel best trial, threshold S/N >= theta, candidates sorted by
+ *      S/N (descending) then pixel index, first K kept  (sections 2.3, 3.1)
+ *
+ * Conventions for every entry point:
+ *   - Every call returns nsfrb_status; no C++ exception crosses the ABI.
+ *     nsfrb_last_error() returns a thread-local message for the last failure.
+ *   - Host pointers are read (or written) during the call only; the library
+ *     copies what it keeps. Device pointers stay owned by the caller.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *
+ * Cube layout: element (t, s, p) of a raw cube is at index
+ *   (t * n_sub + s) * (nx * ny) + p,  with pixel p = y * nx + x,
+ * i.e. [n_time][n_sub][ny*nx], time slowest, pixel fastest.
+ */
+#ifndef NSFRB_H
+#define NSFRB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NSFRB_OK = 0,
+  NSFRB_ERR_INVALID_ARG = 1,   /* a value violates the documented domain        */
+  NSFRB_ERR_UNSUPPORTED = 2,   /* valid, but beyond what this build implements  */
+  NSFRB_ERR_OUT_OF_MEMORY = 3, /* a device or pinned-host allocation failed     */
+  NSFRB_ERR_DEVICE = 4,        /* a HIP runtime or kernel error                  */
+  NSFRB_ERR_NOT_READY = 5,     /* results requested before any run              */
+  NSFRB_ERR_TRUNCATED = 6      /* output capacity smaller than the result count */
+} nsfrb_status;
+
+typedef enum { NSFRB_F32 = 0, NSFRB_F16 = 1, NSFRB_BF16 = 2 } nsfrb_dtype;
+
+typedef enum {
+  NSFRB_NORM_PIXEL_SUBBAND = 0, /* median/MAD per (pixel, sub-band) over time        */
+  NSFRB_NORM_PIXEL = 1,         /* median/MAD per pixel over (time, sub-band)        */
+  NSFRB_NORM_EXTERNAL = 2,      /* caller supplies median and sigma per (p, s)       */
+  NSFRB_NORM_NONE = 3           /* z = x (cast to the store dtype)                   */
+} nsfrb_norm;
+
+/* Search configuration. Host arrays are copied by nsfrb_search_create. */
+typedef struct {
+  uint32_t struct_size;    /* = sizeof(nsfrb_search_config), ABI check           */
+  int32_t nx, ny;          /* image size in pixels, >= 1                          */
+  int32_t n_sub;           /* sub-bands, 1..64                                    */
+  int32_t n_time;          /* samples per series, 1..4096                          */
+  const double* freq_ghz;  /* [n_sub] sub-band frequencies (GHz), finite, > 0      */
+  double f_ref_ghz;        /* reference frequency, >= max(freq_ghz)               */
+  double dt_ms;            /* sampling time (ms), > 0                              */
+  double k_dm_ms;          /* dispersion constant (ms GHz^2 cm^3/pc); 4.15        */
+  int32_t n_dm;            /* DM trials, 1..256                                   */
+  const double* dm;        /* [n_dm] DM trials (pc cm^-3), finite, >= 0           */
+  int32_t n_width;         /* boxcar widths, 1..32                                */
+  const int32_t* width;    /* [n_width] widths in samples, 1..4096                */
+  int32_t in_dtype;        /* nsfrb_dtype of the raw cube                         */
+  int32_t store_dtype;     /* nsfrb_dtype of the normalised cube                  */
+  int32_t norm;            /* nsfrb_norm                                          */
+  float snr_threshold;     /* candidates have best S/N >= this (finite)           */
+  int32_t max_candidates;  /* K of the top-K list, 1..4096                        */
+  int32_t device;          /* HIP device ordinal                                  */
+} nsfrb_search_config;
+
+/* One candidate: the best (DM, width) trial of one pixel. */
+typedef struct {
+  int32_t x, y;            /* pixel coordinates                                   */
+  int32_t dm_index;        /* index into the DM-trial list                        */
+  int32_t width_index;     /* index into the width list                           */
+  int32_t toa;             /* first sample of the boxcar at f_ref                 */
+  float snr;               /* S/N of that trial                                   */
+} nsfrb_candidate;
+
+typedef struct nsfrb_search nsfrb_search; /* opaque handle */
+
+/* Library version string (static storage). */
+const char* nsfrb_version(void);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char* nsfrb_last_error(void);
+
+/* Host-only validation of a configuration (no GPU needed). Returns OK,
+ * INVALID_ARG (e.g. f_ref below the highest frequency, which would make
+ * delays negative; a width < 1; a non-positive dimension) or UNSUPPORTED. */
+nsfrb_status nsfrb_config_validate(const nsfrb_search_config* cfg);
+
+/* Host-only delay table (section 2.2): writes int32 delta[d][s] in samples,
+ * computed in FP64 as ((k_dm*DM) * (1/(f*f) - 1/(f_ref*f_ref))) / dt and
+ * rounded half to even, into host_out[n_dm * n_sub]. */
+nsfrb_status nsfrb_plan_delays(const nsfrb_search_config* cfg, int32_t* host_out);
+
+/* Create a search plan on cfg->device: validates, plans the delay table,
+ * allocates the device workspace (normalised cube, statistics, maps,
+ * candidates) and uploads the tables. On failure *out is NULL. */
+nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfrb_search** out);
+
+/* Release everything the handle owns. NULL is accepted. */
+nsfrb_status nsfrb_search_destroy(nsfrb_search* h);
+
+/* Enqueue one search of the raw device cube d_cube (layout above, in_dtype)
+ * on `stream`; returns without waiting. d_cube must stay valid until the
+ * stream has passed this run (e.g. until nsfrb_candidates_get returns). */
+nsfrb_status nsfrb_search_run(nsfrb_search* h, const void* d_cube, void* stream);
+
+/* Wait for the last run and copy its candidates (sorted by S/N descending,
+ * then pixel index) into host_out[capacity]. *n_written = records copied,
+ * *n_total = all pixels at or above the threshold. Returns TRUNCATED when
+ * capacity < min(n_total, max_candidates), NOT_READY before any run. */
+nsfrb_status nsfrb_candidates_get(nsfrb_search* h, nsfrb_candidate* host_out, int32_t capacity,
+                                  int32_t* n_written, int32_t* n_total);
+
+/* Introspection (each waits for the last run, then copies to host memory). */
+nsfrb_status nsfrb_delay_table_get(const nsfrb_search* h, int32_t* host_out /* [n_dm*n_sub] */);
+/* snr_max / toa: [n_dm][n_width][ny*nx]; -inf / -1 where no window fits. Either may be NULL. */
+nsfrb_status nsfrb_maps_get(nsfrb_search* h, float* snr_max, int32_t* toa);
+/* Per-pixel best trial: S/N, DM index, width index, TOA ([ny*nx] each); any may be NULL. */
+nsfrb_status nsfrb_best_get(nsfrb_search* h, float* snr, int32_t* dm_index, int32_t* width_index,
+                            int32_t* toa);
+/* Noise statistics [ny*nx][n_sub] (FP64). NaN marks a flagged series. */
+nsfrb_status nsfrb_noise_stats_get(nsfrb_search* h, double* med, double* sigma);
+/* EXTERNAL normalisation: statistics used by subsequent runs, [ny*nx][n_sub]. */
+nsfrb_status nsfrb_noise_stats_set(nsfrb_search* h, const double* med, const double* sigma);
+/* Normalised cube in the search layout [ny*nx][n_sub][n_time], store dtype
+ * (2 or 4 bytes per element). */
+nsfrb_status nsfrb_zcube_get(nsfrb_search* h, void* host_out);
+/* Series (or, for NONE/EXTERNAL, samples) flagged as unusable by the last run. */
+nsfrb_status nsfrb_flag_count_get(nsfrb_search* h, int64_t* count);
+
+/* Device pointers of the result buffers owned by the handle (valid until
+ * destroy): snr_max, toa as above. Any out-pointer may be NULL. */
+nsfrb_status nsfrb_maps_device(nsfrb_search* h, float** snr_max, int32_t** toa);
+
+/* Per-stage device time of the last run in milliseconds, measured with HIP
+ * events on the run's stream: [0] statistics + normalisation,
+ * [1] de-dispersion/boxcar/S/N/max, [2] candidates. Requires
+ * nsfrb_profiling_enable(h, 1) before the run. */
+nsfrb_status nsfrb_profiling_enable(nsfrb_search* h, int32_t on);
+nsfrb_status nsfrb_stage_times_get(nsfrb_search* h, float* ms3);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSFRB_H */

@@ -199,3 +199,29 @@ def search(cube_tsp, freqs_ghz, f_ref_ghz, dt_ms, dms, widths, nx,
     return dict(delays=delays, z=z, med=m, sigma=sg, n_flagged=nflag,
                 snr_max=smax, toa=toa, best=best, best_d=bd, best_w=bw,
                 best_toa=bt, candidates=cands, n_total=ntot)
+
+
+def snr_toa_margin_maps(z_tsp, delays, widths):
+    """Like `snr_toa_maps`, plus the gap between the best and the second-best
+    S/N over time (inf where only one window exists, nan where none)."""
+    z = np.asarray(z_tsp, dtype=np.float64)
+    nt, ns, npix = z.shape
+    nd, nw = delays.shape[0], len(widths)
+    smax = np.full((nd, nw, npix), -np.inf)
+    toa = np.full((nd, nw, npix), -1, dtype=np.int32)
+    margin = np.full((nd, nw, npix), np.nan)
+    for d, D in enumerate(dedisperse(z, delays)):
+        for iw, w in enumerate(widths):
+            S = snr_series(D, int(w), ns)
+            if S.shape[0] == 0:
+                continue
+            smax[d, iw] = S.max(axis=0)
+            t = np.argmax(S, axis=0)
+            toa[d, iw] = t.astype(np.int32)
+            if S.shape[0] == 1:
+                margin[d, iw] = np.inf
+            else:
+                S2 = S.copy()
+                S2[t, np.arange(npix)] = -np.inf
+                margin[d, iw] = smax[d, iw] - S2.max(axis=0)
+    return smax, toa, margin

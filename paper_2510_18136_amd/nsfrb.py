@@ -1,0 +1,263 @@
+"""ctypes binding of the C ABI in include/nsfrb.h (argument marshalling only).
+
+Every step of the search runs in the HIP library libnsfrb.so. PyTorch, when
+used by a caller, only provides device buffers and streams: pass
+`tensor.data_ptr()` and `torch.cuda.current_stream().cuda_stream`.
+Loading fails loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libnsfrb.so")
+
+OK, INVALID_ARG, UNSUPPORTED, OUT_OF_MEMORY, DEVICE, NOT_READY, TRUNCATED = range(7)
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY",
+                4: "DEVICE", 5: "NOT_READY", 6: "TRUNCATED"}
+DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
+DTYPE_BYTES = {"f32": 4, "f16": 2, "bf16": 2}
+NORMS = {"pixel_subband": 0, "pixel": 1, "external": 2, "none": 3}
+
+# every symbol declared in include/nsfrb.h
+EXPORTS = [
+    "nsfrb_version", "nsfrb_last_error", "nsfrb_config_validate", "nsfrb_plan_delays",
+    "nsfrb_search_create", "nsfrb_search_destroy", "nsfrb_search_run", "nsfrb_candidates_get",
+    "nsfrb_delay_table_get", "nsfrb_maps_get", "nsfrb_best_get", "nsfrb_noise_stats_get",
+    "nsfrb_noise_stats_set", "nsfrb_zcube_get", "nsfrb_flag_count_get", "nsfrb_maps_device",
+    "nsfrb_profiling_enable", "nsfrb_stage_times_get",
+]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("n_sub", ctypes.c_int32), ("n_time", ctypes.c_int32),
+        ("freq_ghz", ctypes.POINTER(ctypes.c_double)),
+        ("f_ref_ghz", ctypes.c_double), ("dt_ms", ctypes.c_double), ("k_dm_ms", ctypes.c_double),
+        ("n_dm", ctypes.c_int32), ("dm", ctypes.POINTER(ctypes.c_double)),
+        ("n_width", ctypes.c_int32), ("width", ctypes.POINTER(ctypes.c_int32)),
+        ("in_dtype", ctypes.c_int32), ("store_dtype", ctypes.c_int32), ("norm", ctypes.c_int32),
+        ("snr_threshold", ctypes.c_float), ("max_candidates", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+    ]
+
+
+class Candidate(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_int32), ("y", ctypes.c_int32), ("dm_index", ctypes.c_int32),
+                ("width_index", ctypes.c_int32), ("toa", ctypes.c_int32), ("snr", ctypes.c_float)]
+
+
+class NsfrbError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libnsfrb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, pi32 = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
+        pd, pf = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)
+        sig = {
+            "nsfrb_version": ([], ctypes.c_char_p),
+            "nsfrb_last_error": ([], ctypes.c_char_p),
+            "nsfrb_config_validate": ([ctypes.POINTER(Config)], ctypes.c_int),
+            "nsfrb_plan_delays": ([ctypes.POINTER(Config), pi32], ctypes.c_int),
+            "nsfrb_search_create": ([ctypes.POINTER(Config), ctypes.POINTER(vp)], ctypes.c_int),
+            "nsfrb_search_destroy": ([vp], ctypes.c_int),
+            "nsfrb_search_run": ([vp, vp, vp], ctypes.c_int),
+            "nsfrb_candidates_get": ([vp, ctypes.POINTER(Candidate), i32, pi32, pi32], ctypes.c_int),
+            "nsfrb_delay_table_get": ([vp, pi32], ctypes.c_int),
+            "nsfrb_maps_get": ([vp, pf, pi32], ctypes.c_int),
+            "nsfrb_best_get": ([vp, pf, pi32, pi32, pi32], ctypes.c_int),
+            "nsfrb_noise_stats_get": ([vp, pd, pd], ctypes.c_int),
+            "nsfrb_noise_stats_set": ([vp, pd, pd], ctypes.c_int),
+            "nsfrb_zcube_get": ([vp, vp], ctypes.c_int),
+            "nsfrb_flag_count_get": ([vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+            "nsfrb_maps_device": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp)], ctypes.c_int),
+            "nsfrb_profiling_enable": ([vp, i32], ctypes.c_int),
+            "nsfrb_stage_times_get": ([vp, pf], ctypes.c_int),
+            "nsfrb_debug_plan_source": ([ctypes.POINTER(Config), ctypes.c_char_p, i32, i32], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes, f.restype = args, res
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().nsfrb_last_error().decode()
+
+
+def check(status):
+    if status != OK:
+        raise NsfrbError(status, last_error())
+    return status
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+class SearchConfig:
+    """Owns the host arrays behind a C `nsfrb_search_config`."""
+
+    def __init__(self, nx, ny, n_time, freqs_ghz, dms, widths, f_ref_ghz=None, dt_ms=134.2,
+                 k_dm_ms=4.15, in_dtype="f32", store_dtype="f32", norm="pixel_subband",
+                 snr_threshold=6.0, max_candidates=10, device=0):
+        self.freqs = np.ascontiguousarray(freqs_ghz, dtype=np.float64)
+        self.dms = np.ascontiguousarray(dms, dtype=np.float64)
+        self.widths = np.ascontiguousarray(widths, dtype=np.int32)
+        self.nx, self.ny, self.n_time = int(nx), int(ny), int(n_time)
+        self.n_sub = int(self.freqs.size)
+        self.in_dtype, self.store_dtype, self.norm = in_dtype, store_dtype, norm
+        self.max_candidates = int(max_candidates)
+        c = Config()
+        c.struct_size = ctypes.sizeof(Config)
+        c.nx, c.ny, c.n_sub, c.n_time = self.nx, self.ny, self.n_sub, self.n_time
+        c.freq_ghz = _ptr(self.freqs, ctypes.c_double)
+        c.f_ref_ghz = float(self.freqs.max() if f_ref_ghz is None else f_ref_ghz)
+        c.dt_ms, c.k_dm_ms = float(dt_ms), float(k_dm_ms)
+        c.n_dm, c.dm = int(self.dms.size), _ptr(self.dms, ctypes.c_double)
+        c.n_width, c.width = int(self.widths.size), _ptr(self.widths, ctypes.c_int32)
+        c.in_dtype, c.store_dtype, c.norm = DTYPES[in_dtype], DTYPES[store_dtype], NORMS[norm]
+        c.snr_threshold = float(snr_threshold)
+        c.max_candidates = self.max_candidates
+        c.device = int(device)
+        self.c = c
+
+    @property
+    def n_pix(self):
+        return self.nx * self.ny
+
+    def validate(self):
+        return lib().nsfrb_config_validate(ctypes.byref(self.c))
+
+    def delays(self):
+        out = np.zeros((self.dms.size, self.n_sub), dtype=np.int32)
+        check(lib().nsfrb_plan_delays(ctypes.byref(self.c), _ptr(out, ctypes.c_int32)))
+        return out
+
+    def plan_source(self, compile=False):
+        n = lib().nsfrb_debug_plan_source(ctypes.byref(self.c), None, 0, 0)
+        if n < 0:
+            raise NsfrbError(INVALID_ARG, last_error())
+        buf = ctypes.create_string_buffer(n + 1)
+        r = lib().nsfrb_debug_plan_source(ctypes.byref(self.c), buf, n + 1, 1 if compile else 0)
+        if r < 0:
+            raise NsfrbError(DEVICE, last_error())
+        return buf.value.decode()
+
+
+class Search:
+    """A search plan on one GPU (nsfrb_search_create / run / candidates_get)."""
+
+    def __init__(self, cfg: SearchConfig):
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        check(lib().nsfrb_search_create(ctypes.byref(cfg.c), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nsfrb_search_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def run(self, d_cube_ptr, stream=0):
+        check(lib().nsfrb_search_run(self.h, ctypes.c_void_p(int(d_cube_ptr)), ctypes.c_void_p(int(stream))))
+
+    def candidates(self, capacity=None):
+        cap = self.cfg.max_candidates if capacity is None else int(capacity)
+        arr = (Candidate * max(cap, 1))()
+        nw, nt = ctypes.c_int32(), ctypes.c_int32()
+        st = lib().nsfrb_candidates_get(self.h, arr, cap, ctypes.byref(nw), ctypes.byref(nt))
+        if st not in (OK, TRUNCATED):
+            check(st)
+        recs = [dict(x=c.x, y=c.y, dm_index=c.dm_index, width_index=c.width_index, toa=c.toa, snr=c.snr)
+                for c in arr[:nw.value]]
+        return recs, nt.value, st
+
+    def maps(self):
+        c = self.cfg
+        shape = (c.dms.size, c.widths.size, c.n_pix)
+        snr = np.zeros(shape, np.float32)
+        toa = np.zeros(shape, np.int32)
+        check(lib().nsfrb_maps_get(self.h, _ptr(snr, ctypes.c_float), _ptr(toa, ctypes.c_int32)))
+        return snr, toa
+
+    def best(self):
+        n = self.cfg.n_pix
+        s = np.zeros(n, np.float32)
+        d, w, t = (np.zeros(n, np.int32) for _ in range(3))
+        check(lib().nsfrb_best_get(self.h, _ptr(s, ctypes.c_float), _ptr(d, ctypes.c_int32),
+                                   _ptr(w, ctypes.c_int32), _ptr(t, ctypes.c_int32)))
+        return s, d, w, t
+
+    def noise_stats(self):
+        n = (self.cfg.n_pix, self.cfg.n_sub)
+        med, sig = np.zeros(n), np.zeros(n)
+        check(lib().nsfrb_noise_stats_get(self.h, _ptr(med, ctypes.c_double), _ptr(sig, ctypes.c_double)))
+        return med, sig
+
+    def set_noise_stats(self, med, sigma):
+        med = np.ascontiguousarray(med, dtype=np.float64)
+        sig = np.ascontiguousarray(sigma, dtype=np.float64)
+        check(lib().nsfrb_noise_stats_set(self.h, _ptr(med, ctypes.c_double), _ptr(sig, ctypes.c_double)))
+
+    def zcube(self):
+        """Normalised cube [p][s][t] as float64 values of the store dtype."""
+        c = self.cfg
+        n = c.n_pix * c.n_sub * c.n_time
+        if c.store_dtype == "f32":
+            raw = np.zeros(n, np.float32)
+        else:
+            raw = np.zeros(n, np.uint16)
+        check(lib().nsfrb_zcube_get(self.h, raw.ctypes.data_as(ctypes.c_void_p)))
+        if c.store_dtype == "f16":
+            vals = raw.view(np.float16).astype(np.float64)
+        elif c.store_dtype == "bf16":
+            vals = (raw.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        else:
+            vals = raw.astype(np.float64)
+        return vals.reshape(c.n_pix, c.n_sub, c.n_time), raw.reshape(c.n_pix, c.n_sub, c.n_time)
+
+    def flag_count(self):
+        v = ctypes.c_int64()
+        check(lib().nsfrb_flag_count_get(self.h, ctypes.byref(v)))
+        return v.value
+
+    def profiling(self, on=True):
+        check(lib().nsfrb_profiling_enable(self.h, 1 if on else 0))
+
+    def stage_times_ms(self):
+        out = np.zeros(3, np.float32)
+        check(lib().nsfrb_stage_times_get(self.h, _ptr(out, ctypes.c_float)))
+        return out
+
+    def delay_table(self):
+        out = np.zeros((self.cfg.dms.size, self.cfg.n_sub), np.int32)
+        check(lib().nsfrb_delay_table_get(self.h, _ptr(out, ctypes.c_int32)))
+        return out

@@ -16,15 +16,38 @@ Sky model: a pulse of DM `dm` that starts at sample t0 at the reference
 f_ref^-2)/dt) -- the cold-plasma dispersion law, rounded to whole samples as
 the synthetic workload prescribes.
 """
+import os
+
 import numpy as np
 
 
-def noise_cube(nt, ns, npix, seed, sigma_pix=None, dtype=np.float32):
-    """Gaussian noise [t][s][p]; sigma per pixel (default 1)."""
-    rng = np.random.default_rng(seed)
-    cube = rng.standard_normal((nt, ns, npix), dtype=np.float32)
-    if sigma_pix is not None:
-        cube *= np.asarray(sigma_pix, dtype=np.float32)[None, None, :]
+def noise_cube(nt, ns, npix, seed, sigma_pix=None, dtype=np.float32, block=64):
+    """Gaussian noise [t][s][p]; sigma per pixel (default 1).
+
+    Time blocks of `block` samples draw from independent PCG64 streams spawned
+    from `seed` (so blocks can be filled by parallel threads; the result does
+    not depend on the thread count).
+    """
+    import concurrent.futures as cf
+    cube = np.empty((nt, ns, npix), dtype=np.float32)
+    nblk = (nt + block - 1) // block
+    seqs = np.random.SeedSequence(seed).spawn(nblk)
+    sig = None if sigma_pix is None else np.asarray(sigma_pix, dtype=np.float32)[None, None, :]
+
+    def fill(b):
+        rng = np.random.default_rng(seqs[b])
+        sl = cube[b * block:(b + 1) * block]
+        rng.standard_normal(out=sl, dtype=np.float32)
+        if sig is not None:
+            np.multiply(sl, sig, out=sl)
+
+    workers = min(16, os.cpu_count() or 1, nblk)
+    if workers > 1 and cube.size > (1 << 22):
+        with cf.ThreadPoolExecutor(workers) as ex:
+            list(ex.map(fill, range(nblk)))
+    else:
+        for b in range(nblk):
+            fill(b)
     return cube.astype(dtype, copy=False)
 
 

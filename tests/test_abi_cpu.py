@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+The library must load, export every function declared in include/nsfrb.h,
+reject invalid configurations, compute the delay table bit-exactly like the
+oracle, and generate + compile the plan-specialised search kernel.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.delays import delay_table
+from paper_2510_18136_amd import nsfrb, synth
+from tests._lib import ensure_built
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return ensure_built()
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "nsfrb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nsfrb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    declared = header_functions()
+    assert len(declared) >= 18
+    assert sorted(nsfrb.EXPORTS) == declared
+    for name in declared:
+        assert hasattr(L, name), name
+    assert b"gfx950" in L.nsfrb_version()
+
+
+def c2_config(**kw):
+    args = dict(nx=256, ny=256, n_time=2048, freqs_ghz=synth.C2_FREQS, dms=np.linspace(0, 4000, 32),
+                widths=synth.widths_pow2(1024, (1200,)))
+    args.update(kw)
+    return nsfrb.SearchConfig(**args)
+
+
+def test_valid_config_and_struct_size(L):
+    c = c2_config()
+    assert c.validate() == nsfrb.OK, nsfrb.last_error()
+    c.c.struct_size += 4
+    assert c.validate() == nsfrb.INVALID_ARG
+    assert "struct_size" in nsfrb.last_error()
+
+
+@pytest.mark.parametrize("kw,status,msg", [
+    (dict(f_ref_ghz=1.4), nsfrb.INVALID_ARG, "f_ref"),
+    (dict(widths=[1, 0, 4]), nsfrb.INVALID_ARG, "widths"),
+    (dict(nx=0), nsfrb.INVALID_ARG, "dimensions"),
+    (dict(dms=[0.0, -5.0]), nsfrb.INVALID_ARG, "DM"),
+    (dict(dt_ms=0.0), nsfrb.INVALID_ARG, "dt_ms"),
+    (dict(max_candidates=0), nsfrb.INVALID_ARG, "max_candidates"),
+    (dict(norm="pixel"), nsfrb.UNSUPPORTED, "PIXEL"),
+    (dict(n_time=5000), nsfrb.UNSUPPORTED, "n_time"),
+    (dict(snr_threshold=float("nan")), nsfrb.INVALID_ARG, "snr_threshold"),
+])
+def test_invalid_configs(L, kw, status, msg):
+    c = c2_config(**kw)
+    assert c.validate() == status
+    assert msg in nsfrb.last_error()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_delay_table_bit_exact_vs_oracle(L, seed):
+    rng = np.random.default_rng(seed)
+    ns = int(rng.integers(1, 33))
+    freqs = np.sort(rng.uniform(0.3, 2.0, ns))
+    f_ref = freqs.max() + (0.0 if seed % 2 == 0 else rng.uniform(0, 0.1))
+    dms = rng.uniform(0, 3000, int(rng.integers(1, 64)))
+    dt = float(rng.uniform(0.5, 200.0))
+    c = nsfrb.SearchConfig(8, 8, 4096, freqs, dms, [1], f_ref_ghz=f_ref, dt_ms=dt)
+    np.testing.assert_array_equal(c.delays(), delay_table(freqs, f_ref, dt, dms))
+
+
+def test_delay_table_workloads(L):
+    c = c2_config()
+    np.testing.assert_array_equal(c.delays(), delay_table(synth.C2_FREQS, synth.C2_FREQS.max(), 134.2,
+                                                          np.linspace(0, 4000, 32)))
+    c1 = nsfrb.SearchConfig(32, 32, 64, synth.C1_FREQS, np.linspace(0, 1000, 8), [1, 2, 4, 8, 16])
+    np.testing.assert_array_equal(c1.delays(), delay_table(synth.C1_FREQS, synth.C1_FREQS.max(), 134.2,
+                                                           np.linspace(0, 1000, 8)))
+
+
+def test_forced_allocation_failure(L, monkeypatch):
+    monkeypatch.setenv("NSFRB_FORCE_ALLOC_FAIL", "1")
+    with pytest.raises(nsfrb.NsfrbError) as e:
+        nsfrb.Search(c2_config())
+    assert e.value.status == nsfrb.OUT_OF_MEMORY
+
+
+def test_chain_plan_composes_non_power_of_two_widths(L):
+    src = c2_config().plan_source()
+    assert "constexpr int kC = 33;" in src
+    # 1200 = 16 + 32 + 128 + 1024 placed end to end: offsets 16, 48, 176
+    for frag in ("copy_arr(acc0, a0)", "shift_add<16>(acc0", "shift_add<48>(acc0", "shift_add<176>(acc0",
+                 "rep(11, acc0)"):
+        assert frag in src
+    src = nsfrb.SearchConfig(4, 4, 100, [1.3, 1.4], [0.0], [3, 200, 7, 64]).plan_source()
+    assert "rep.invalid(1)" in src          # 200 > n_time
+    assert "rep(3, a0)" in src             # 64 = level 6 (even level -> a0)
+
+
+@pytest.mark.parametrize("store", ["f32", "f16", "bf16"])
+def test_search_kernel_compiles_for_gfx950(L, store):
+    c = c2_config(store_dtype=store)
+    c.plan_source(compile=True)
+    c1 = nsfrb.SearchConfig(32, 32, 64, synth.C1_FREQS, np.linspace(0, 1000, 8), [1, 2, 3, 5, 16, 63],
+                            store_dtype=store)
+    c1.plan_source(compile=True)
+
+
+def test_too_many_open_accumulators_is_unsupported(L):
+    c = nsfrb.SearchConfig(4, 4, 1024, [1.3, 1.4], [0.0], [1023, 1021, 1019, 1017])
+    with pytest.raises(nsfrb.NsfrbError):
+        c.plan_source()

@@ -1,0 +1,271 @@
+"""GPU parity of the HIP search against the FP64 oracle (needs an MI355X).
+
+Rules (the oracle and the HIP path share no code; inputs are seeded):
+  * delay table, noise statistics and the normalised cube: bit-exact;
+  * S/N maps: |GPU - oracle| <= 1e-4 (FP32 store);
+  * TOA, best (DM, width) and candidate membership: exact wherever the
+    oracle's margin (best vs second best over t, over (d, w), or |best - theta|)
+    exceeds EPS = 2e-4; near-ties within EPS may go either way;
+  * integer-valued cubes (sums exact in any order): every index exact.
+"""
+import numpy as np
+import pytest
+
+from oracle import search as osr
+from oracle.delays import delay_table
+from paper_2510_18136_amd import nsfrb, synth
+from tests._lib import ensure_built
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+EPS = 2e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    ensure_built()
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+
+
+def to_device(cube, dtype):
+    if dtype == "f32":
+        return torch.from_numpy(np.ascontiguousarray(cube, dtype=np.float32)).cuda()
+    if dtype == "f16":
+        return torch.from_numpy(np.ascontiguousarray(cube, dtype=np.float16)).cuda()
+    bits = osr.round_f32_to_bf16(cube.astype(np.float32)).view(np.uint32) >> 16
+    return torch.from_numpy(bits.astype(np.uint16).view(np.int16)).cuda()
+
+
+def input_values(cube, dtype):
+    """Exact values the library sees for a host cube given in `dtype`."""
+    if dtype == "f32":
+        return cube.astype(np.float32)
+    if dtype == "f16":
+        return cube.astype(np.float16).astype(np.float32)
+    return osr.round_f32_to_bf16(cube.astype(np.float32))
+
+
+def run_gpu(cube, cfg, ext=None):
+    x = to_device(cube, cfg.in_dtype)
+    with nsfrb.Search(cfg) as s:
+        if ext is not None:
+            s.set_noise_stats(*ext)
+        print(f"[gpu] run nx={cfg.nx} ny={cfg.ny} ns={cfg.n_sub} nt={cfg.n_time} nd={cfg.dms.size} "
+              f"w={list(cfg.widths)} store={cfg.store_dtype} norm={cfg.norm}", flush=True)
+        s.run(x.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        cands, ntot, st = s.candidates()
+        snr, toa = s.maps()
+        bs, bd, bw, bt = s.best()
+        out = dict(cands=cands, n_total=ntot, status=st, snr=snr, toa=toa, best=bs, best_d=bd, best_w=bw,
+                   best_t=bt, delays=s.delay_table(), flags=s.flag_count(), z=s.zcube()[0])
+        if cfg.norm == "pixel_subband":
+            out["med"], out["sig"] = s.noise_stats()
+    torch.cuda.synchronize()
+    return out
+
+
+def oracle_run(cube, cfg, ext=None):
+    med, sig = (None, None) if ext is None else ext
+    r = osr.search(input_values(cube, cfg.in_dtype), cfg.freqs, float(cfg.c.f_ref_ghz), cfg.c.dt_ms, cfg.dms,
+                   list(cfg.widths), cfg.nx, norm=cfg.norm, store=cfg.store_dtype,
+                   theta=float(cfg.c.snr_threshold), k_max=cfg.max_candidates, med=med, sigma=sig)
+    sm, toa, margin = osr.snr_toa_margin_maps(r["z"], r["delays"], list(cfg.widths))
+    assert np.array_equal(sm, r["snr_max"], equal_nan=True)
+    r["margin"] = margin
+    return r
+
+
+def dw_margin(smax):
+    nd, nw, npix = smax.shape
+    flat = smax.reshape(nd * nw, npix)
+    srt = np.sort(np.where(np.isfinite(flat), flat, -np.inf), axis=0)
+    return srt[-1] - srt[-2] if nd * nw > 1 else np.full(npix, np.inf)
+
+
+def compare(g, o, cfg, tol=TOL, eps=EPS, exact_z=True):
+    np.testing.assert_array_equal(g["delays"], o["delays"])
+    if exact_z:
+        zo = np.transpose(o["z"], (2, 1, 0))          # [t][s][p] -> [p][s][t]
+        np.testing.assert_array_equal(g["z"], zo)
+    if "med" in g:
+        np.testing.assert_array_equal(g["med"], o["med"])
+        np.testing.assert_array_equal(g["sig"], o["sigma"])
+    assert g["flags"] == o["n_flagged"]
+    fin = np.isfinite(o["snr_max"])
+    assert np.array_equal(np.isfinite(g["snr"]), fin)
+    assert (g["toa"][~fin] == -1).all()
+    err = np.abs(g["snr"][fin].astype(np.float64) - o["snr_max"][fin])
+    assert err.max(initial=0.0) <= tol, f"max |dS/N| {err.max()}"
+    clear = fin & (o["margin"] > eps)
+    np.testing.assert_array_equal(g["toa"][clear], o["toa"][clear])
+    # best trial per pixel
+    m = dw_margin(o["snr_max"])
+    okp = np.isfinite(o["best"])
+    clear_p = okp & (m > eps)
+    np.testing.assert_array_equal(g["best_d"][clear_p], o["best_d"][clear_p])
+    np.testing.assert_array_equal(g["best_w"][clear_p], o["best_w"][clear_p])
+    ok_t = clear_p & (o["margin"][o["best_d"].clip(0), o["best_w"].clip(0), np.arange(o["best"].size)] > eps)
+    np.testing.assert_array_equal(g["best_t"][ok_t], o["best_t"][ok_t])
+    assert np.abs(g["best"][okp] - o["best"][okp]).max(initial=0.0) <= tol
+    # candidates: total count, then the ranked list where it is unambiguous
+    theta = float(cfg.c.snr_threshold)
+    near = np.isfinite(o["best"]) & (np.abs(o["best"] - theta) <= eps)
+    if not near.any():
+        assert g["n_total"] == o["n_total"]
+    oc, gc = o["candidates"], g["cands"]
+    assert len(gc) == min(cfg.max_candidates, g["n_total"])
+    for i, (a, b) in enumerate(zip(gc, oc)):
+        assert abs(a["snr"] - b["snr"]) <= tol
+        gaps = [abs(b["snr"] - c["snr"]) for j, c in enumerate(oc) if j != i]
+        if min(gaps, default=np.inf) > eps:
+            assert (a["x"], a["y"]) == (b["x"], b["y"])
+
+
+def c1_cfg(**kw):
+    a = dict(nx=32, ny=32, n_time=64, freqs_ghz=synth.C1_FREQS, dms=np.linspace(0, 1000, 8),
+             widths=[1, 2, 4, 8, 16])
+    a.update(kw)
+    return nsfrb.SearchConfig(**a)
+
+
+def test_config1_tiny_fp32():
+    cube, meta = synth.config1()
+    cfg = c1_cfg()
+    g, o = run_gpu(cube, cfg), oracle_run(cube, cfg)
+    compare(g, o, cfg)
+    assert o["n_total"] == 0 and g["n_total"] == 0     # expected S/N 4 < 6
+
+
+def test_config1_bright_pulse_candidate():
+    cube, meta = synth.config1(amp=4.0)
+    cfg = c1_cfg()
+    g, o = run_gpu(cube, cfg), oracle_run(cube, cfg)
+    compare(g, o, cfg)
+    assert g["n_total"] >= 1
+    c = g["cands"][0]
+    assert (c["x"], c["y"]) == (16, 16) and c["dm_index"] == 3 and c["toa"] == 20
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_shapes_ragged(seed):
+    rng = np.random.default_rng(100 + seed)
+    nx, ny = int(rng.integers(1, 23)), int(rng.integers(1, 13))
+    ns = int(rng.integers(1, 17))
+    nt = int(rng.choice([1, 7, 63, 64, 65, 100, 257, 511, 700, 1000]))
+    freqs = np.sort(rng.uniform(1.2, 1.5, ns))
+    nd = int(rng.integers(1, 20))
+    dms = np.sort(rng.uniform(0, 3000, nd))
+    widths = sorted(set(int(w) for w in rng.integers(1, max(2, nt + 5), size=int(rng.integers(1, 7)))))
+    rng.shuffle(widths)
+    store = ["f32", "f16", "bf16"][seed % 3]
+    cube = rng.standard_normal((nt, ns, nx * ny)).astype(np.float32) * rng.uniform(0.5, 2.0)
+    cube += rng.uniform(-3, 3)
+    cfg = nsfrb.SearchConfig(nx, ny, nt, freqs, dms, widths, store_dtype=store, snr_threshold=3.0,
+                             max_candidates=int(rng.integers(1, 40)))
+    if cfg.validate() != nsfrb.OK:
+        pytest.skip(nsfrb.last_error())
+    try:
+        cfg.plan_source()
+    except nsfrb.NsfrbError as e:
+        pytest.skip(str(e))
+    g, o = run_gpu(cube, cfg), oracle_run(cube, cfg)
+    compare(g, o, cfg, tol=TOL if store == "f32" else 2e-4)
+
+
+def test_integer_cube_exact_indices():
+    rng = np.random.default_rng(7)
+    nt, ns, nx, ny = 300, 8, 12, 9
+    cube = rng.integers(-6, 7, size=(nt, ns, nx * ny)).astype(np.float32)
+    freqs = np.linspace(1.311, 1.499, ns)
+    dms = np.linspace(0, 3000, 11)
+    widths = [1, 2, 3, 4, 8, 13, 64, 100, 256]
+    cfg = nsfrb.SearchConfig(nx, ny, nt, freqs, dms, widths, norm="none", snr_threshold=4.0, max_candidates=50)
+    g, o = run_gpu(cube, cfg), oracle_run(cube, cfg)
+    compare(g, o, cfg, eps=0.0)
+    fin = np.isfinite(o["snr_max"])
+    np.testing.assert_array_equal(g["toa"], o["toa"])       # sums are exact: first maximum is exact
+    assert np.abs(g["snr"][fin] - o["snr_max"][fin]).max() <= 2e-6 * np.abs(o["snr_max"][fin]).max()
+
+
+def test_integer_ties_first_time_and_smallest_trial():
+    # constant cube: every window of a width ties; TOA is the first valid sample
+    nt, ns = 40, 4
+    cube = np.ones((nt, ns, 5), dtype=np.float32)
+    cfg = nsfrb.SearchConfig(5, 1, nt, synth.C1_FREQS, [0.0, 500.0, 1000.0], [1, 2, 4], norm="none",
+                             snr_threshold=1.0)
+    g, o = run_gpu(cube, cfg), oracle_run(cube, cfg)
+    assert (g["toa"][np.isfinite(o["snr_max"])] == 0).all()
+    compare(g, o, cfg, eps=0.0)
+    # S/N grows with sqrt(w): best is the widest width, smallest DM
+    assert (g["best_d"] == 0).all() and (g["best_w"] == 2).all()
+
+
+def test_no_valid_window_and_invalid_trials():
+    nt, ns = 20, 4
+    rng = np.random.default_rng(3)
+    cube = rng.standard_normal((nt, ns, 6)).astype(np.float32)
+    freqs = synth.C1_FREQS
+    dms = [0.0, 4000.0, 20000.0]                 # the last one delays beyond the cube
+    cfg = nsfrb.SearchConfig(3, 2, nt, freqs, dms, [1, 5, 19, 20, 21], snr_threshold=0.5)
+    g, o = run_gpu(cube, cfg), oracle_run(cube, cfg)
+    assert (delay_table(freqs, freqs.max(), 134.2, dms)[2].max() >= nt)
+    assert np.isinf(g["snr"][2]).all() and (g["toa"][2] == -1).all()
+    assert np.isinf(g["snr"][:, 4]).all()          # width 21 > n_time
+    compare(g, o, cfg)
+
+
+def test_external_stats_closed_form():
+    ns, nt = 16, 256
+    freqs = synth.C2_FREQS
+    dms = np.linspace(0, 4000, 32)
+    delays = delay_table(freqs, freqs.max(), 134.2, dms)
+    cube = np.zeros((nt, ns, 4), dtype=np.float32)
+    A, w, sigma = 2.0, 24, 1.5
+    synth.inject_boxcar(cube, 1, 77, delays[20], w, A * sigma)
+    med = np.zeros((4, ns))
+    sig = np.full((4, ns), sigma)
+    cfg = nsfrb.SearchConfig(2, 2, nt, freqs, dms, [1, 8, 16, 24, 32], norm="external", snr_threshold=6.0)
+    g, o = run_gpu(cube, cfg, ext=(med, sig)), oracle_run(cube, cfg, ext=(med, sig))
+    compare(g, o, cfg)
+    assert abs(g["snr"][20, 3, 1] - A * np.sqrt(w * ns)) <= 1e-4
+    assert g["toa"][20, 3, 1] == 77
+    assert g["cands"][0]["x"] == 1 and g["cands"][0]["dm_index"] == 20
+
+
+def test_nan_input_is_flagged():
+    rng = np.random.default_rng(9)
+    cube = rng.standard_normal((64, 4, 20)).astype(np.float32)
+    cube[10, 2, 3] = np.nan
+    cube[:, 1, 7] = np.inf
+    cfg = c1_cfg(nx=5, ny=4, snr_threshold=2.0)
+    g, o = run_gpu(cube, cfg), oracle_run(cube, cfg)
+    assert g["flags"] == 2
+    compare(g, o, cfg)
+
+
+def test_truncation_and_not_ready():
+    cube, meta = synth.config1(amp=6.0)
+    cfg = c1_cfg(snr_threshold=3.0, max_candidates=8)
+    x = to_device(cube, "f32")
+    with nsfrb.Search(cfg) as s:
+        with pytest.raises(nsfrb.NsfrbError) as e:
+            s.candidates()
+        assert e.value.status == nsfrb.NOT_READY
+        s.run(x.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        recs, ntot, st = s.candidates(capacity=2)
+        assert ntot > 2 and len(recs) == 2 and st == nsfrb.TRUNCATED
+        full, ntot2, st2 = s.candidates()
+        assert st2 == nsfrb.OK and full[:2] == recs and len(full) == min(8, ntot)
+
+
+def test_deterministic_runs():
+    rng = np.random.default_rng(5)
+    cube = rng.standard_normal((512, 16, 24 * 8)).astype(np.float32)
+    cfg = nsfrb.SearchConfig(24, 8, 512, synth.C2_FREQS, np.linspace(0, 4000, 32),
+                             [1, 2, 4, 8, 16, 32, 64, 100, 128, 256, 500], snr_threshold=3.0)
+    a, b = run_gpu(cube, cfg), run_gpu(cube, cfg)
+    for k in ("snr", "toa", "best", "best_d", "best_w", "best_t", "z", "med", "sig"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    assert a["cands"] == b["cands"]
