@@ -50,6 +50,12 @@ typedef enum {
 typedef enum { NSFRB_F32 = 0, NSFRB_F16 = 1, NSFRB_BF16 = 2 } nsfrb_dtype;
 
 typedef enum {
+  NSFRB_LAYOUT_TSP = 0, /* raw cube [n_time][n_sub][ny*nx] (images as they arrive)             */
+  NSFRB_LAYOUT_PST = 1  /* already normalised, in the search layout [ny*nx][n_sub][n_time];
+                           requires NSFRB_NORM_NONE and in_dtype == store_dtype; searched in place */
+} nsfrb_layout;
+
+typedef enum {
   NSFRB_NORM_PIXEL_SUBBAND = 0, /* median/MAD per (pixel, sub-band) over time        */
   NSFRB_NORM_PIXEL = 1,         /* median/MAD per pixel over (time, sub-band)        */
   NSFRB_NORM_EXTERNAL = 2,      /* caller supplies median and sigma per (p, s)       */
@@ -76,6 +82,7 @@ typedef struct {
   float snr_threshold;     /* candidates have best S/N >= this (finite)           */
   int32_t max_candidates;  /* K of the top-K list, 1..4096                        */
   int32_t device;          /* HIP device ordinal                                  */
+  int32_t layout;          /* nsfrb_layout of the input cube                      */
 } nsfrb_search_config;
 
 /* One candidate: the best (DM, width) trial of one pixel. */
@@ -152,6 +159,56 @@ nsfrb_status nsfrb_maps_device(nsfrb_search* h, float** snr_max, int32_t** toa);
  * nsfrb_profiling_enable(h, 1) before the run. */
 nsfrb_status nsfrb_profiling_enable(nsfrb_search* h, int32_t on);
 nsfrb_status nsfrb_stage_times_get(nsfrb_search* h, float* ms3);
+
+/* Plan of the search kernel: info[0] samples per lane, info[1] pixels per
+ * workgroup (chosen by the autotuner), info[2] LDS row length, info[3] LDS
+ * bytes per workgroup. */
+nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* info);
+
+/* ------------------------------------------------------------------ batch
+ * Many cubes of uneven shape searched together (the process server of
+ * section 2.2 batches search tasks per timescale). All configurations must
+ * share the DM trials, widths, store dtype, normalisation, layout, input
+ * dtype and device; nx, ny, n_sub, n_time and frequencies may differ.
+ * nsfrb_batch_run enqueues the statistics of every cube, then ONE persistent
+ * search launch whose workgroups stride over the work items of all cubes,
+ * then the candidates of every cube. The sequence is captured once as a
+ * hipGraph and replayed while the cube pointers stay the same.
+ * Results are bitwise equal to nsfrb_batch_run_separate, which runs the same
+ * kernel body with one plain launch per cube. */
+typedef struct nsfrb_batch nsfrb_batch;
+
+nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int32_t n_cubes, nsfrb_batch** out);
+nsfrb_status nsfrb_batch_destroy(nsfrb_batch* b);
+/* d_cubes: host array of n_cubes device pointers (caller-owned, valid until the run completes). */
+nsfrb_status nsfrb_batch_run(nsfrb_batch* b, const void* const* d_cubes, void* stream);
+nsfrb_status nsfrb_batch_run_separate(nsfrb_batch* b, const void* const* d_cubes, void* stream);
+/* Graph capture on (default 1) or off. */
+nsfrb_status nsfrb_batch_use_graph(nsfrb_batch* b, int32_t on);
+/* Same contract as nsfrb_candidates_get / nsfrb_maps_get, for cube `cube`. */
+nsfrb_status nsfrb_batch_candidates_get(nsfrb_batch* b, int32_t cube, nsfrb_candidate* host_out,
+                                        int32_t capacity, int32_t* n_written, int32_t* n_total);
+nsfrb_status nsfrb_batch_maps_get(nsfrb_batch* b, int32_t cube, float* snr_max, int32_t* toa);
+/* info[0] work items, [1] persistent grid size, [2] LDS bytes, [3] kernel
+ * classes, [4] 1 if the last run replayed a captured graph. */
+nsfrb_status nsfrb_batch_info_get(nsfrb_batch* b, int64_t* info);
+
+/* ------------------------------------------------------------ generator
+ * Synthetic input on the device (for workloads too large to build on the
+ * host). Gaussian noise N(0, sigma^2): element e of the cube (in its layout
+ * order) takes value 4*(e/4) ... from one Philox4x32-10 block (Salmon et al.
+ * 2011) with counter (e/4, 0, 0, 0) and key (seed low, seed high), turned into
+ * two Box-Muller pairs. dtype: nsfrb_dtype; layout: nsfrb_layout. */
+nsfrb_status nsfrb_generate_noise(void* d_out, int32_t dtype, int32_t layout, int32_t n_pix, int32_t n_sub,
+                                  int32_t n_time, uint64_t seed, float sigma, void* stream);
+/* Add `amp` to samples t0 + offsets[s] ... + width - 1 of every sub-band s of
+ * pixel `pixel` (samples outside the cube are skipped); host_offsets[n_sub]. */
+nsfrb_status nsfrb_inject_boxcar(void* d_cube, int32_t dtype, int32_t layout, int32_t n_pix, int32_t n_sub,
+                                 int32_t n_time, int32_t pixel, int32_t t0, int32_t width, float amp,
+                                 const int32_t* host_offsets, void* stream);
+/* Raw Philox4x32-10 words: block i (4 words) of counter (i, 0, 0, 0), key
+ * (seed low, seed high); d_out[4 * n_blocks] uint32. */
+nsfrb_status nsfrb_philox_fill(uint32_t* d_out, int64_t n_blocks, uint64_t seed, void* stream);
 
 #ifdef __cplusplus
 }

@@ -6,29 +6,30 @@
 // TOA; section 2.3 keeps those S/N and TOA maps for all pixels, widths and DM
 // trials.
 //
-// This file is compiled at plan time with the sample count per lane (kC), the
-// store dtype (ST) and the boxcar plan (nsfrb_chain) fixed as constants; the
-// generated prologue defines them. DM trials, delays, n_sub and n_t stay
-// runtime values.
+// This file is compiled at plan time. The generated prologue fixes the store
+// dtype (ST), the number of widths (NSFRB_NW) and the shape classes; the
+// generated boxcar plan (nsfrb_chain) follows this file. DM trials, delays,
+// n_sub and n_t stay runtime values.
 //
 // Layout and work split (gfx950, wave64):
-//  * one workgroup of kWaves waves per pixel; the pixel's normalised series
-//    z[s][0..n_t) is staged in LDS, one row per sub-band of rs samples; samples
-//    at and beyond n_t hold -inf, so any window that reaches past the end of a
-//    de-dispersed series sums to -inf and can never be a maximum;
-//  * wave w takes DM trials d = w, w + kWaves, ...; lane l holds the kC
-//    consecutive samples t = kC*l + c (kC is odd, so lanes hit distinct LDS
-//    banks at any delay);
+//  * a workgroup of kWaves waves takes PIX pixels at a time; their normalised
+//    series z[s][0..n_t) are staged in LDS, one row per sub-band of rs
+//    samples; samples at and beyond n_t hold -inf, so any window that reaches
+//    past the end of a de-dispersed series sums to -inf and is never a maximum;
+//  * kWaves/PIX waves share a pixel and split its DM trials round-robin (the
+//    "DM chunk" of a wave is every (kWaves/PIX)-th trial);
+//  * lane l holds the C consecutive samples t = C*l + c (C is odd, so lanes hit
+//    distinct LDS banks at any delay);
 //  * D_d[t] = sum_s z[s][t + delta[d][s]] is formed in registers (FP32);
 //  * boxcars use the pairwise doubling B_2w[t] = B_w[t] + B_w[t+w]; a width
 //    that is not a power of two is the sum of the power-of-two windows of its
 //    binary digits placed end to end. Each output is a balanced sum, so the
 //    FP32 error grows with log2(w) rather than w;
-//  * a window shifted by k samples is read from register (c+k) mod kC of lane
-//    l + (c+k)/kC: same lane, a DPP wave shift by one lane, or ds_bpermute.
+//  * a window shifted by k samples is read from register (c+k) mod C of lane
+//    l + (c+k)/C: the same lane, a DPP wave shift by one lane, or ds_bpermute.
 
 #ifndef NSFRB_RTC_PROLOGUE
-#error "compile through the search plan: the prologue defines kC, ST and nsfrb_chain"
+#error "compile through the search plan: the prologue defines ST, NSFRB_NW and the shape classes"
 #endif
 
 namespace nsfrb {
@@ -47,14 +48,14 @@ __device__ __forceinline__ float lane_ahead(float x, int q, int l) {
   return (l + q < kWave) ? __int_as_float(v) : kNegInf;
 }
 
-// out[c] = a[c] + b at sample t + K, for t = kC*l + c.
-template <int K>
-__device__ __forceinline__ void shift_add(float (&out)[kC], const float (&a)[kC], const float (&b)[kC]) {
+// out[c] = a[c] + b at sample t + K, for t = C*l + c.
+template <int K, int C>
+__device__ __forceinline__ void shift_add(float (&out)[C], const float (&a)[C], const float (&b)[C]) {
   const int l = lane_id();
 #pragma unroll
-  for (int c = 0; c < kC; ++c) {
-    const int q = (c + K) / kC;
-    const int r = (c + K) % kC;
+  for (int c = 0; c < C; ++c) {
+    const int q = (c + K) / C;
+    const int r = (c + K) % C;
     float v;
     if (q == 0) v = b[r];
     else if (q == 1) v = lane_next(b[r]);
@@ -63,9 +64,10 @@ __device__ __forceinline__ void shift_add(float (&out)[kC], const float (&a)[kC]
   }
 }
 
-__device__ __forceinline__ void copy_arr(float (&out)[kC], const float (&a)[kC]) {
+template <int C>
+__device__ __forceinline__ void copy_arr(float (&out)[C], const float (&a)[C]) {
 #pragma unroll
-  for (int c = 0; c < kC; ++c) out[c] = a[c];
+  for (int c = 0; c < C; ++c) out[c] = a[c];
 }
 
 __device__ __forceinline__ float wave_max_f(float v) {
@@ -91,110 +93,172 @@ __device__ __forceinline__ bool better(float s, int d, int w, const Best& b) {
 }
 
 // Max over all samples of a boxcar array and the first sample reaching it.
-__device__ __forceinline__ void max_first(const float (&b)[kC], float& M, int& T) {
+template <int C>
+__device__ __forceinline__ void max_first(const float (&b)[C], float& M, int& T) {
   const int l = lane_id();
   float m = kNegInf;
   int idx = -1;
 #pragma unroll
-  for (int c = 0; c < kC; ++c) {
+  for (int c = 0; c < C; ++c) {
     const bool gt = b[c] > m;
     m = gt ? b[c] : m;
     idx = gt ? c : idx;
   }
   M = wave_max_f(m);
-  const int cand = (idx >= 0 && m == M) ? kC * l + idx : 0x7fffffff;
+  const int cand = (idx >= 0 && m == M) ? C * l + idx : 0x7fffffff;
   T = wave_min_i(cand);
   if (!(M > kNegInf)) T = -1;
 }
 
-struct Reporter {
+// Where one cube's results go.
+struct CubeOut {
   const float* norms;
   float* snr_max;
   int* toa;
-  int n_pix, p, d, nw;
+  int n_pix;
+};
+
+struct Reporter {
+  CubeOut o;
+  int p, d;
   Best best;
   __device__ __forceinline__ void emit(int iw, float M, int T) {
-    const float s = (M > kNegInf) ? M / norms[iw] : kNegInf;
+    const float s = (M > kNegInf) ? M / o.norms[iw] : kNegInf;
     if (lane_id() == 0) {
-      const size_t o = ((size_t)d * nw + iw) * n_pix + p;
-      snr_max[o] = s;
-      toa[o] = T;
+      const size_t idx = ((size_t)d * NSFRB_NW + iw) * o.n_pix + p;
+      o.snr_max[idx] = s;
+      o.toa[idx] = T;
     }
     if (better(s, d, iw, best)) best = Best{s, d, iw, T};
   }
-  __device__ __forceinline__ void operator()(int iw, const float (&b)[kC]) {
+  template <int C>
+  __device__ __forceinline__ void operator()(int iw, const float (&b)[C]) {
     float M;
     int T;
-    max_first(b, M, T);
+    max_first<C>(b, M, T);
     emit(iw, M, T);
   }
   __device__ __forceinline__ void invalid(int iw) { emit(iw, kNegInf, -1); }
 };
 
+// Everything the search needs about one cube (also the batch descriptor).
+struct CubeDesc {
+  const ST* z;              // [n_pix][n_sub][n_t]
+  const int* delays;        // [n_dm][n_sub]
+  const int* dmax;          // [n_dm]
+  const float* norms;       // [NSFRB_NW]
+  float* snr_max;           // [n_dm][NSFRB_NW][n_pix]
+  int* toa;
+  float* best_s;            // [n_pix]
+  int* best_d;
+  int* best_w;
+  int* best_t;
+  int n_pix, n_sub, n_t, n_dm, rs, cls;
+  long long item_begin;     // first work item of this cube in a batch
+};
+
 }  // namespace nsfrb
 
-// The boxcar plan, generated per width list after this file: it forms every
-// power-of-two window level from the de-dispersed series held in `cur` and
-// calls rep(width_index, window_sums) once per width.
-template <class R>
-__device__ void nsfrb_chain(float (&cur)[kC], R& rep);
+// The boxcar plan, generated per width list after this file: pass `pass`
+// forms the power-of-two window levels it needs from the de-dispersed series
+// held in `cur` and calls rep(width_index, window_sums) for its widths; the
+// passes together report every width once (NSFRB_NPASS passes).
+template <int C, class R>
+__device__ void nsfrb_chain(int pass, float (&cur)[C], R& rep);
 
-extern "C" __global__ __launch_bounds__(nsfrb::kWaves * nsfrb::kWave) void nsfrb_search_kernel(
-    const ST* __restrict__ z, const int* __restrict__ delays, const int* __restrict__ dmaxv,
-    const float* __restrict__ norms, int n_pix, int n_sub, int n_t, int n_dm, int rs,
-    float* __restrict__ snr_max, int* __restrict__ toa, float* __restrict__ best_s,
-    int* __restrict__ best_d, int* __restrict__ best_w, int* __restrict__ best_t) {
-  using namespace nsfrb;
-  extern __shared__ unsigned char lds_raw[];
-  ST* zl = reinterpret_cast<ST*>(lds_raw);
-  __shared__ Best red[kWaves];
+namespace nsfrb {
+
+// One work item: PIX consecutive pixels starting at p0 of one cube.
+// Requires all kWaves waves of the workgroup (it contains barriers).
+template <int C, int PIX>
+__device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl, Best* red) {
+  constexpr int WPP = kWaves / PIX;        // waves per pixel
   const int wv = threadIdx.x / kWave;
   const int l = lane_id();
+  const int slot = wv / WPP;               // which pixel of the group
+  const int wq = wv % WPP;                 // this wave's DM chunk: d = wq, wq + WPP, ...
+  const int rs = cd.rs, n_sub = cd.n_sub, n_t = cd.n_t;
   const ST neg = from_f32<ST>(kNegInf);
-
-  for (int blk = blockIdx.x; blk < n_pix; blk += gridDim.x) {
-    // pixels of one XCD are contiguous (workgroups are dealt round-robin over 8 XCDs)
-    int p = blk;
-    if ((n_pix & 7) == 0 && gridDim.x == n_pix) p = (blk & 7) * (n_pix >> 3) + (blk >> 3);
-    // ---- stage z[p] into LDS, rows of rs samples, -inf beyond n_t
-    const ST* zp = z + (size_t)p * n_sub * n_t;
-    for (int s = 0; s < n_sub; ++s) {
-      const ST* src = zp + (size_t)s * n_t;
-      ST* dst = zl + s * rs;
-      for (int u = threadIdx.x; u < rs; u += blockDim.x) dst[u] = (u < n_t) ? src[u] : neg;
+  // ---- stage the group's rows into LDS, -inf beyond n_t
+  for (int k = 0; k < PIX; ++k) {
+    const int p = p0 + k;
+    ST* dstp = zl + (size_t)k * n_sub * rs;
+    if (p < cd.n_pix) {
+      const ST* zp = cd.z + (size_t)p * n_sub * n_t;
+      for (int s = 0; s < n_sub; ++s) {
+        const ST* src = zp + (size_t)s * n_t;
+        ST* dst = dstp + s * rs;
+        for (int u = threadIdx.x; u < rs; u += blockDim.x) dst[u] = (u < n_t) ? src[u] : neg;
+      }
     }
-    __syncthreads();
-
-    Reporter rep{norms, snr_max, toa, n_pix, p, 0, NSFRB_NW, Best{kNegInf, -1, -1, -1}};
-    for (int d = wv; d < n_dm; d += kWaves) {
+  }
+  __syncthreads();
+  const int p = p0 + slot;
+  Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, p, 0, Best{kNegInf, -1, -1, -1}};
+  if (p < cd.n_pix) {
+    const ST* zbase = zl + (size_t)slot * n_sub * rs;
+    for (int d = wq; d < cd.n_dm; d += WPP) {
       rep.d = d;
-      if (dmaxv[d] >= n_t) {
+      if (cd.dmax[d] >= n_t) {
         for (int iw = 0; iw < NSFRB_NW; ++iw) rep.invalid(iw);
         continue;
       }
-      float cur[kC];
+      for (int pass = 0; pass < NSFRB_NPASS; ++pass) {
+        float cur[C];
 #pragma unroll
-      for (int c = 0; c < kC; ++c) cur[c] = 0.f;
-      for (int s = 0; s < n_sub; ++s) {
-        const int dl = delays[d * n_sub + s];
-        const ST* row = zl + s * rs + dl + kC * l;
+        for (int c = 0; c < C; ++c) cur[c] = 0.f;
+        for (int s = 0; s < n_sub; ++s) {
+          const int dl = cd.delays[d * n_sub + s];
+          const ST* row = zbase + s * rs + dl + C * l;
 #pragma unroll
-        for (int c = 0; c < kC; ++c) cur[c] += to_f32(row[c]);
+          for (int c = 0; c < C; ++c) cur[c] += to_f32(row[c]);
+        }
+        nsfrb_chain<C>(pass, cur, rep);
       }
-      nsfrb_chain(cur, rep);
     }
-    if (l == 0) red[wv] = rep.best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      Best b = red[0];
-      for (int k = 1; k < kWaves; ++k)
-        if (better(red[k].s, red[k].d, red[k].w, b)) b = red[k];
-      const bool ok = b.s > kNegInf;
-      best_s[p] = ok ? b.s : kNegInf;
-      best_d[p] = ok ? b.d : -1;
-      best_w[p] = ok ? b.w : -1;
-      best_t[p] = ok ? b.t : -1;
-    }
-    __syncthreads();
   }
+  if (l == 0) red[wv] = rep.best;
+  __syncthreads();
+  if (threadIdx.x < PIX && p0 + (int)threadIdx.x < cd.n_pix) {
+    const int k = threadIdx.x;
+    Best b = red[k * WPP];
+    for (int j = 1; j < WPP; ++j)
+      if (better(red[k * WPP + j].s, red[k * WPP + j].d, red[k * WPP + j].w, b)) b = red[k * WPP + j];
+    const bool ok = b.s > kNegInf;
+    const int pp = p0 + k;
+    cd.best_s[pp] = ok ? b.s : kNegInf;
+    cd.best_d[pp] = ok ? b.d : -1;
+    cd.best_w[pp] = ok ? b.w : -1;
+    cd.best_t[pp] = ok ? b.t : -1;
+  }
+  __syncthreads();
+}
+
+}  // namespace nsfrb
+
+// Single cube: work item i covers pixels [i*PIX, i*PIX + PIX); items are dealt
+// so that the items running on one XCD at a time are neighbours.
+template <int C, int PIX>
+__device__ __forceinline__ void search_cube(const nsfrb::CubeDesc& cd) {
+  using namespace nsfrb;
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ Best red[kWaves];
+  ST* zl = reinterpret_cast<ST*>(lds_raw);
+  const int n_items = (cd.n_pix + PIX - 1) / PIX;
+  for (int blk = blockIdx.x; blk < n_items; blk += gridDim.x) {
+    int item = blk;
+    if ((n_items & 7) == 0 && (int)gridDim.x == n_items) item = (blk & 7) * (n_items >> 3) + (blk >> 3);
+    search_group<C, PIX>(cd, item * PIX, zl, red);
+  }
+}
+
+// Persistent batch: every workgroup strides over the concatenated work items of
+// all cubes; each item dispatches to the body compiled for its cube's class.
+__device__ __forceinline__ int find_cube(const nsfrb::CubeDesc* descs, int n_cubes, long long item) {
+  int lo = 0, hi = n_cubes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }

@@ -320,6 +320,11 @@ __global__ void k_zero_u64(unsigned long long* p) {
   if (threadIdx.x == 0) p[0] = 0ull;
 }
 
+hipError_t launch_zero_u64(unsigned long long* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, p);
+  return hipGetLastError();
+}
+
 hipError_t launch_stats(const StatsLaunch& a, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, a.flag_count);
   switch (a.in_dtype) {

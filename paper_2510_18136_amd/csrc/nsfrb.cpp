@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <atomic>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -100,6 +102,9 @@ static nsfrb_status validate(const nsfrb_search_config* c) {
     return fail(NSFRB_ERR_INVALID_ARG, "unknown dtype");
   if (c->norm < 0 || c->norm > 3) return fail(NSFRB_ERR_INVALID_ARG, "unknown normalisation mode");
   if (c->norm == NSFRB_NORM_PIXEL) return fail(NSFRB_ERR_UNSUPPORTED, "NSFRB_NORM_PIXEL is not implemented");
+  if (c->layout != NSFRB_LAYOUT_TSP && c->layout != NSFRB_LAYOUT_PST) return fail(NSFRB_ERR_INVALID_ARG, "unknown layout");
+  if (c->layout == NSFRB_LAYOUT_PST && (c->norm != NSFRB_NORM_NONE || c->in_dtype != c->store_dtype))
+    return fail(NSFRB_ERR_INVALID_ARG, "NSFRB_LAYOUT_PST needs NSFRB_NORM_NONE and in_dtype == store_dtype");
   if (!std::isfinite(c->snr_threshold)) return fail(NSFRB_ERR_INVALID_ARG, "snr_threshold must be finite");
   if (c->max_candidates < 1 || c->max_candidates > kMaxCand)
     return fail(NSFRB_ERR_INVALID_ARG, "max_candidates must be in 1..4096");
@@ -129,122 +134,149 @@ extern "C" nsfrb_status nsfrb_plan_delays(const nsfrb_search_config* cfg, int32_
 }
 
 // ------------------------------------------------- search plan (codegen)
-struct SearchPlan {
-  int C = 0;               // samples per lane (odd), 64*C >= n_time
-  int rs = 0;              // LDS row length in samples
-  size_t lds_bytes = 0;
-  std::string source;      // generated translation unit
+struct KernelClass {
+  int C;     // samples per lane
+  int PIX;   // pixels per workgroup
 };
-
-static int lanes_per_sample_count(int n_time) {
+std::string single_kernel_name(const KernelClass& k);
+// Samples per lane: odd, so 64 lanes reading rows at a common delay hit
+// distinct LDS banks; 64*C >= n_time.
+static int samples_per_lane(int n_time) {
   int c = (n_time + 63) / 64;
   if ((c & 1) == 0) c += 1;
   return c;
 }
+static int row_len(int C, int dmax_search) { return 64 * C + dmax_search + 1; }
+static size_t lds_bytes_for(int pix, int n_sub, int rs, int store) {
+  return (size_t)pix * n_sub * rs * dtype_size(store);
+}
 
 // Emit the boxcar plan: power-of-two levels by pairwise doubling, other
-// widths as sums of the level windows of their binary digits.
-static nsfrb_status gen_chain(const std::vector<int>& widths, int n_time, std::string& out) {
+// widths as sums of the level windows of their binary digits. A width that
+// is not a power of two needs an accumulator from its lowest to its highest
+// binary digit; widths are split into passes so that at most
+// kMaxAccumulators accumulators are open at any level of a pass (each extra
+// pass re-forms the de-dispersed series). Power-of-two widths go in pass 0.
+static nsfrb_status gen_chain(const std::vector<int>& widths, std::string& out, int* npass_out = nullptr) {
   const int nw = (int)widths.size();
-  int maxb = -1;
-  for (int w : widths)
-    if (w <= n_time) {
-      int b = 0;
-      while ((2 << b) <= w) ++b;
-      maxb = b > maxb ? b : maxb;
-    }
-  std::ostringstream o;
-  o << "template <class R>\n__device__ void nsfrb_chain(float (&a0)[kC], R& rep) {\n";
-  o << "  using namespace nsfrb;\n  float a1[kC];\n";
-  // accumulators for non-power-of-two widths: [lowest bit, highest bit]
-  struct Acc { int iw, w, lo, hi, slot, off; };
+  struct Acc { int iw, w, lo, hi, pass, slot, off; };
   std::vector<Acc> accs;
   for (int iw = 0; iw < nw; ++iw) {
     const int w = widths[iw];
-    if (w > n_time || (w & (w - 1)) == 0) continue;
-    int lo = __builtin_ctz((unsigned)w), hi = 31 - __builtin_clz((unsigned)w);
-    accs.push_back({iw, w, lo, hi, -1, 0});
+    if ((w & (w - 1)) == 0) continue;
+    const int lo = __builtin_ctz((unsigned)w), hi = 31 - __builtin_clz((unsigned)w);
+    accs.push_back({iw, w, lo, hi, -1, -1, 0});
   }
-  // slot allocation by interval scheduling
-  int nslots = 0;
-  std::vector<int> slot_free_after;   // level after which the slot is free
+  std::sort(accs.begin(), accs.end(), [](const Acc& x, const Acc& y) { return x.lo < y.lo || (x.lo == y.lo && x.hi < y.hi); });
+  // passes[p][slot] = last level the slot is busy through
+  std::vector<std::vector<int>> passes(1);
   for (auto& a : accs) {
-    for (int s = 0; s < (int)slot_free_after.size(); ++s)
-      if (slot_free_after[s] < a.lo) { a.slot = s; slot_free_after[s] = a.hi; break; }
-    if (a.slot < 0) { a.slot = (int)slot_free_after.size(); slot_free_after.push_back(a.hi); }
-  }
-  nslots = (int)slot_free_after.size();
-  if (nslots > kMaxAccumulators)
-    return fail(NSFRB_ERR_UNSUPPORTED, "too many non-power-of-two widths open at once (max 3)");
-  for (int s = 0; s < nslots; ++s) o << "  float acc" << s << "[kC];\n";
-  for (int iw = 0; iw < nw; ++iw)
-    if (widths[iw] > n_time) o << "  rep.invalid(" << iw << ");\n";
-  for (int b = 0; b <= maxb; ++b) {
-    const char* cur = (b & 1) ? "a1" : "a0";
-    const char* nxt = (b & 1) ? "a0" : "a1";
-    o << "  // level " << b << ": windows of " << (1 << b) << " samples in " << cur << "\n";
-    for (int iw = 0; iw < nw; ++iw)
-      if (widths[iw] == (1 << b)) o << "  rep(" << iw << ", " << cur << ");\n";
-    for (auto& a : accs) {
-      if (!((a.w >> b) & 1)) continue;
-      if (b == a.lo) {
-        o << "  copy_arr(acc" << a.slot << ", " << cur << ");\n";
-      } else {
-        o << "  shift_add<" << a.off << ">(acc" << a.slot << ", acc" << a.slot << ", " << cur << ");\n";
+    for (int p = 0; p < (int)passes.size() && a.pass < 0; ++p) {
+      for (int s = 0; s < (int)passes[p].size(); ++s)
+        if (passes[p][s] < a.lo) { a.pass = p; a.slot = s; passes[p][s] = a.hi; break; }
+      if (a.pass < 0 && (int)passes[p].size() < kMaxAccumulators) {
+        a.pass = p; a.slot = (int)passes[p].size(); passes[p].push_back(a.hi);
       }
-      a.off += 1 << b;
-      if (b == a.hi) o << "  rep(" << a.iw << ", acc" << a.slot << ");\n";
     }
-    if (b < maxb) o << "  shift_add<" << (1 << b) << ">(" << nxt << ", " << cur << ", " << cur << ");\n";
+    if (a.pass < 0) { passes.push_back({a.hi}); a.pass = (int)passes.size() - 1; a.slot = 0; }
   }
-  o << "}\n";
+  const int npass = (int)passes.size();
+  std::ostringstream o;
+  o << "template <int C, class R>\n__device__ void nsfrb_chain(int pass, float (&a0)[C], R& rep) {\n";
+  o << "  using namespace nsfrb;\n  float a1[C];\n";
+  for (int s = 0; s < kMaxAccumulators; ++s) o << "  float acc" << s << "[C];\n";
+  o << "  switch (pass) {\n";
+  for (int p = 0; p < npass; ++p) {
+    int maxb = 0;
+    for (int iw = 0; iw < nw; ++iw) {
+      if (p == 0 && (widths[iw] & (widths[iw] - 1)) == 0) maxb = std::max(maxb, __builtin_ctz((unsigned)widths[iw]));
+    }
+    for (auto& a : accs)
+      if (a.pass == p) maxb = std::max(maxb, a.hi);
+    o << "  case " << p << ": {\n";
+    for (int b = 0; b <= maxb; ++b) {
+      const char* cur = (b & 1) ? "a1" : "a0";
+      const char* nxt = (b & 1) ? "a0" : "a1";
+      o << "    // level " << b << ": windows of " << (1 << b) << " samples in " << cur << "\n";
+      if (p == 0)
+        for (int iw = 0; iw < nw; ++iw)
+          if (widths[iw] == (1 << b)) o << "    rep(" << iw << ", " << cur << ");\n";
+      for (auto& a : accs) {
+        if (a.pass != p || !((a.w >> b) & 1)) continue;
+        if (b == a.lo) o << "    copy_arr(acc" << a.slot << ", " << cur << ");\n";
+        else o << "    shift_add<" << a.off << ">(acc" << a.slot << ", acc" << a.slot << ", " << cur << ");\n";
+        a.off += 1 << b;
+        if (b == a.hi) o << "    rep(" << a.iw << ", acc" << a.slot << ");\n";
+      }
+      if (b < maxb) o << "    shift_add<" << (1 << b) << ">(" << nxt << ", " << cur << ", " << cur << ");\n";
+    }
+    o << "  } break;\n";
+  }
+  o << "  default: break;\n  }\n}\n";
   out = o.str();
+  if (npass_out) *npass_out = npass;
   return NSFRB_OK;
 }
 
-static nsfrb_status build_plan(const nsfrb_search_config& c, int dmax_search, SearchPlan& plan) {
-  plan.C = lanes_per_sample_count(c.n_time);
-  plan.rs = 64 * plan.C + dmax_search + 1;
-  plan.lds_bytes = (size_t)c.n_sub * plan.rs * dtype_size(c.store_dtype);
-  if (plan.lds_bytes > kLdsBudget)
-    return fail(NSFRB_ERR_UNSUPPORTED, "n_sub x (padded n_time + max delay) does not fit in LDS for this store dtype");
-  std::vector<int> widths(c.width, c.width + c.n_width);
-  std::string chain;
-  nsfrb_status st = gen_chain(widths, c.n_time, chain);
-  if (st != NSFRB_OK) return st;
-  const char* st_name = c.store_dtype == DT_F32 ? "float" : (c.store_dtype == DT_F16 ? "_Float16" : "nsfrb::bf16_t");
+static const char* store_type_name(int store) {
+  return store == DT_F32 ? "float" : (store == DT_F16 ? "_Float16" : "nsfrb::bf16_t");
+}
+
+// Translation unit with single-cube kernels for (C, PIX) pairs and, if
+// `batch` is set, the persistent batch kernel dispatching over `classes`.
+static std::string gen_source(int store, int nw, int npass, const std::string& chain,
+                              const std::vector<KernelClass>& single, const std::vector<KernelClass>& batch) {
   std::ostringstream o;
   o << "#define NSFRB_RTC_PROLOGUE 1\n#include \"device_common.h\"\n";
-  o << "typedef " << st_name << " ST;\n";
-  o << "constexpr int kC = " << plan.C << ";\n";
-  o << "#define NSFRB_NW " << c.n_width << "\n";
+  o << "#define NSFRB_NPASS " << npass << "\n";
+  o << "typedef " << store_type_name(store) << " ST;\n";
+  o << "#define NSFRB_NW " << nw << "\n";
   o << "#include \"k_search_body.h\"\n";
   o << chain;
-  plan.source = o.str();
-  return NSFRB_OK;
+  for (const auto& k : single)
+    o << "extern \"C\" __global__ __launch_bounds__(512) void " << single_kernel_name(k)
+      << "(nsfrb::CubeDesc cd) { search_cube<" << k.C << ", " << k.PIX << ">(cd); }\n";
+  if (!batch.empty()) {
+    o << "extern \"C\" __global__ __launch_bounds__(512) void nsfrb_batch_kernel("
+         "const nsfrb::CubeDesc* __restrict__ descs, int n_cubes, long long n_items) {\n"
+         "  using namespace nsfrb;\n"
+         "  extern __shared__ unsigned char lds_raw[];\n"
+         "  __shared__ Best red[kWaves];\n"
+         "  ST* zl = reinterpret_cast<ST*>(lds_raw);\n"
+         "  for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {\n"
+         "    const int ci = find_cube(descs, n_cubes, it);\n"
+         "    const CubeDesc cd = descs[ci];\n"
+         "    const int local = (int)(it - cd.item_begin);\n"
+         "    switch (cd.cls) {\n";
+    for (size_t i = 0; i < batch.size(); ++i)
+      o << "      case " << i << ": search_group<" << batch[i].C << ", " << batch[i].PIX << ">(cd, local * "
+        << batch[i].PIX << ", zl, red); break;\n";
+    o << "      default: break;\n    }\n  }\n}\n";
+  }
+  return o.str();
 }
 
-// Compiled kernels, shared by every handle on a device.
-struct CompiledKernel {
+std::string single_kernel_name(const KernelClass& k) {
+  return "nsfrb_search_c" + std::to_string(k.C) + "_p" + std::to_string(k.PIX);
+}
+
+// Compiled modules, shared by every handle on a device.
+struct CompiledModule {
   hipModule_t mod = nullptr;
-  hipFunction_t fn = nullptr;
 };
 static std::mutex g_rtc_mu;
-static std::map<std::pair<int, std::string>, CompiledKernel> g_rtc_cache;
+static std::map<std::pair<int, std::string>, CompiledModule> g_rtc_cache;
 
-static nsfrb_status compile_search(int device, const std::string& src, hipFunction_t* fn) {
-  std::lock_guard<std::mutex> lk(g_rtc_mu);
-  auto key = std::make_pair(device, src);
-  auto it = g_rtc_cache.find(key);
-  if (it != g_rtc_cache.end()) { *fn = it->second.fn; return NSFRB_OK; }
+static const char* kRtcOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
+                                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+
+static nsfrb_status rtc_compile(const std::string& src, std::vector<char>& code) {
   hiprtcProgram prog;
   const char* hdr_names[] = {"device_common.h", "k_search_body.h"};
   const char* hdr_src[] = {kRtcDeviceCommon, kRtcSearchBody};
   if (hiprtcCreateProgram(&prog, src.c_str(), "nsfrb_search.hip", 2, hdr_src, hdr_names) != HIPRTC_SUCCESS)
     return fail(NSFRB_ERR_DEVICE, "hiprtcCreateProgram failed");
-  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
-                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
-  hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+  hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof(kRtcOpts) / sizeof(kRtcOpts[0])), kRtcOpts);
   if (r != HIPRTC_SUCCESS) {
     size_t n = 0;
     hiprtcGetProgramLogSize(prog, &n);
@@ -255,7 +287,7 @@ static nsfrb_status compile_search(int device, const std::string& src, hipFuncti
   }
   size_t sz = 0;
   hiprtcGetCodeSize(prog, &sz);
-  std::vector<char> code(sz);
+  code.resize(sz);
   hiprtcGetCode(prog, code.data());
   hiprtcDestroyProgram(&prog);
   const char* dump = std::getenv("NSFRB_DUMP_CODE");
@@ -263,12 +295,50 @@ static nsfrb_status compile_search(int device, const std::string& src, hipFuncti
     FILE* f = std::fopen(dump, "wb");
     if (f) { std::fwrite(code.data(), 1, code.size(), f); std::fclose(f); }
   }
-  CompiledKernel ck;
-  HIP_TRY(hipModuleLoadData(&ck.mod, code.data()));
-  HIP_TRY(hipModuleGetFunction(&ck.fn, ck.mod, "nsfrb_search_kernel"));
-  g_rtc_cache[key] = ck;
-  *fn = ck.fn;
   return NSFRB_OK;
+}
+
+nsfrb_status load_module(int device, const std::string& src, hipModule_t* mod) {
+  std::lock_guard<std::mutex> lk(g_rtc_mu);
+  auto key = std::make_pair(device, src);
+  auto it = g_rtc_cache.find(key);
+  if (it != g_rtc_cache.end()) { *mod = it->second.mod; return NSFRB_OK; }
+  std::vector<char> code;
+  nsfrb_status st = rtc_compile(src, code);
+  if (st != NSFRB_OK) return st;
+  CompiledModule cm;
+  HIP_TRY(hipModuleLoadData(&cm.mod, code.data()));
+  g_rtc_cache[key] = cm;
+  *mod = cm.mod;
+  return NSFRB_OK;
+}
+
+static int max_delay_searchable(const std::vector<int32_t>& delays, int n_dm, int n_sub, int n_time,
+                                std::vector<int32_t>* dmaxv) {
+  int dmax_search = 0;
+  if (dmaxv) dmaxv->assign(n_dm, 0);
+  for (int d = 0; d < n_dm; ++d) {
+    int m = 0;
+    for (int s = 0; s < n_sub; ++s) m = std::max(m, (int)delays[(size_t)d * n_sub + s]);
+    if (dmaxv) (*dmaxv)[d] = m;
+    if (m < n_time) dmax_search = std::max(dmax_search, m);
+  }
+  return dmax_search;
+}
+
+// Pixels per workgroup that fit in LDS, best first by the default heuristic
+// (enough waves per pixel to cover the DM trials).
+static std::vector<int> pix_candidates(int n_dm, int n_sub, int rs, int store) {
+  std::vector<int> out;
+  for (int pix : {1, 2, 4, 8})
+    if (lds_bytes_for(pix, n_sub, rs, store) <= kLdsBudget) out.push_back(pix);
+  std::sort(out.begin(), out.end(), [&](int a, int b) {
+    const int wa = 8 / a, wb = 8 / b;           // waves per pixel
+    const bool fa = wa <= n_dm, fb = wb <= n_dm;  // no idle waves
+    if (fa != fb) return fa;
+    return fa ? a < b : a > b;
+  });
+  return out;
 }
 
 // Host-only entry: generate (and optionally compile) the specialised search
@@ -277,46 +347,26 @@ extern "C" int nsfrb_debug_plan_source(const nsfrb_search_config* cfg, char* out
   if (validate(cfg) != NSFRB_OK) return -1;
   std::vector<int32_t> dl;
   compute_delays(*cfg, dl);
-  int dmax_search = 0;
-  for (int d = 0; d < cfg->n_dm; ++d) {
-    int m = 0;
-    for (int s = 0; s < cfg->n_sub; ++s) m = dl[(size_t)d * cfg->n_sub + s] > m ? dl[(size_t)d * cfg->n_sub + s] : m;
-    if (m < cfg->n_time && m > dmax_search) dmax_search = m;
+  const int dmax_search = max_delay_searchable(dl, cfg->n_dm, cfg->n_sub, cfg->n_time, nullptr);
+  const int C = samples_per_lane(cfg->n_time);
+  const int rs = row_len(C, dmax_search);
+  std::vector<int> pix = pix_candidates(cfg->n_dm, cfg->n_sub, rs, cfg->store_dtype);
+  if (pix.empty()) {
+    fail(NSFRB_ERR_UNSUPPORTED, "a pixel's rows do not fit in LDS");
+    return -1;
   }
-  SearchPlan plan;
-  if (build_plan(*cfg, dmax_search, plan) != NSFRB_OK) return -1;
-  if (out && cap > 0) {
-    std::snprintf(out, (size_t)cap, "%s", plan.source.c_str());
-  }
+  std::string chain;
+  int npass = 1;
+  if (gen_chain(std::vector<int>(cfg->width, cfg->width + cfg->n_width), chain, &npass) != NSFRB_OK) return -1;
+  std::vector<KernelClass> ks;
+  for (int p : pix) ks.push_back({C, p});
+  const std::string src = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, ks);
+  if (out && cap > 0) std::snprintf(out, (size_t)cap, "%s", src.c_str());
   if (compile) {
-    hiprtcProgram prog;
-    const char* hdr_names[] = {"device_common.h", "k_search_body.h"};
-    const char* hdr_src[] = {kRtcDeviceCommon, kRtcSearchBody};
-    hiprtcCreateProgram(&prog, plan.source.c_str(), "nsfrb_search.hip", 2, hdr_src, hdr_names);
-    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
-                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
-    hiprtcResult r = hiprtcCompileProgram(prog, 7, opts);
-    if (r != HIPRTC_SUCCESS) {
-      size_t n = 0;
-      hiprtcGetProgramLogSize(prog, &n);
-      std::string log(n + 1, '\0');
-      hiprtcGetProgramLog(prog, &log[0]);
-      g_last_error = log;
-      hiprtcDestroyProgram(&prog);
-      return -2;
-    }
-    size_t sz = 0;
-    hiprtcGetCodeSize(prog, &sz);
-    const char* dump = std::getenv("NSFRB_DUMP_CODE");
-    if (dump && *dump) {
-      std::vector<char> code(sz);
-      hiprtcGetCode(prog, code.data());
-      FILE* f = std::fopen(dump, "wb");
-      if (f) { std::fwrite(code.data(), 1, code.size(), f); std::fclose(f); }
-    }
-    hiprtcDestroyProgram(&prog);
+    std::vector<char> code;
+    if (rtc_compile(src, code) != NSFRB_OK) return -2;
   }
-  return (int)plan.source.size();
+  return (int)src.size();
 }
 
 // ------------------------------------------------------------------ handle
@@ -325,8 +375,13 @@ struct nsfrb_search {
   std::vector<double> freqs, dms;
   std::vector<int32_t> widths, delays, dmaxv;
   int n_pix = 0, device = 0;
-  SearchPlan plan;
+  int C = 0, rs = 0, pix = 1;          // chosen kernel class and LDS row length
+  size_t lds_bytes = 0;
+  std::string source;                  // generated search translation unit
+  hipModule_t mod = nullptr;
   hipFunction_t search_fn = nullptr;
+  std::vector<int> tuned_pix;          // candidates timed by the autotuner
+  std::vector<float> tuned_ms;
   // device buffers
   int32_t *d_delays = nullptr, *d_dmax = nullptr;
   float* d_norms = nullptr;
@@ -347,6 +402,7 @@ struct nsfrb_search {
   hipEvent_t done = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool profiling = false, ran = false, ext_set = false;
+  const void* last_z = nullptr;        // normalised cube searched by the last run
 };
 
 template <typename T>
@@ -370,6 +426,8 @@ static void release(nsfrb_search* h) {
   delete h;
 }
 
+static nsfrb_status autotune(nsfrb_search* h, const std::vector<int>& pix);
+
 extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfrb_search** out) {
   g_last_error.clear();
   if (!out) return fail(NSFRB_ERR_INVALID_ARG, "out is NULL");
@@ -387,28 +445,31 @@ extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfr
   h->n_pix = cfg->nx * cfg->ny;
   h->device = cfg->device;
   compute_delays(h->cfg, h->delays);
-  h->dmaxv.assign(cfg->n_dm, 0);
-  int dmax_search = 0;
-  for (int d = 0; d < cfg->n_dm; ++d) {
-    int m = 0;
-    for (int s = 0; s < cfg->n_sub; ++s) m = std::max(m, (int)h->delays[(size_t)d * cfg->n_sub + s]);
-    h->dmaxv[d] = m;
-    if (m < cfg->n_time) dmax_search = std::max(dmax_search, m);
-  }
-  st = build_plan(h->cfg, dmax_search, h->plan);
+  const int dmax_search = max_delay_searchable(h->delays, cfg->n_dm, cfg->n_sub, cfg->n_time, &h->dmaxv);
+  h->C = samples_per_lane(cfg->n_time);
+  h->rs = row_len(h->C, dmax_search);
+  std::vector<int> pix = pix_candidates(cfg->n_dm, cfg->n_sub, h->rs, cfg->store_dtype);
+  if (pix.empty())
+    return fail(NSFRB_ERR_UNSUPPORTED, "n_sub x (padded n_time + max delay) does not fit in LDS for this store dtype");
+  std::string chain;
+  int npass = 1;
+  st = gen_chain(h->widths, chain, &npass);
   if (st != NSFRB_OK) return st;
+  std::vector<KernelClass> ks;
+  for (int p : pix) ks.push_back({h->C, p});
+  h->source = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, {});
   const char* force = std::getenv("NSFRB_FORCE_ALLOC_FAIL");
   if (force && std::atoi(force) != 0) return fail(NSFRB_ERR_OUT_OF_MEMORY, "allocation failure forced by NSFRB_FORCE_ALLOC_FAIL");
 
   HIP_TRY(hipSetDevice(h->device));
-  st = compile_search(h->device, h->plan.source, &h->search_fn);
+  st = load_module(h->device, h->source, &h->mod);
   if (st != NSFRB_OK) return st;
   const size_t n_pix = (size_t)h->n_pix, ns = (size_t)cfg->n_sub, nt = (size_t)cfg->n_time;
   const size_t nmaps = (size_t)cfg->n_dm * cfg->n_width * n_pix;
   HIP_TRY(dalloc(&h->d_delays, h->delays.size()));
   HIP_TRY(dalloc(&h->d_dmax, h->dmaxv.size()));
   HIP_TRY(dalloc(&h->d_norms, (size_t)cfg->n_width));
-  HIP_TRY(hipMalloc(&h->d_z, n_pix * ns * nt * dtype_size(cfg->store_dtype)));
+  if (cfg->layout == NSFRB_LAYOUT_TSP) HIP_TRY(hipMalloc(&h->d_z, n_pix * ns * nt * dtype_size(cfg->store_dtype)));
   HIP_TRY(dalloc(&h->d_med, n_pix * ns));
   HIP_TRY(dalloc(&h->d_sig, n_pix * ns));
   if (cfg->norm == NSFRB_NORM_EXTERNAL) {
@@ -436,6 +497,9 @@ extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfr
   HIP_TRY(hipMemcpy(h->d_dmax, h->dmaxv.data(), h->dmaxv.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->d_norms, norms.data(), norms.size() * sizeof(float), hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(h->d_flags, 0, sizeof(unsigned long long)));
+  st = autotune(h.get(), pix);
+  if (st != NSFRB_OK) return st;
+  h->lds_bytes = lds_bytes_for(h->pix, cfg->n_sub, h->rs, cfg->store_dtype);
   *out = h.release();
   return NSFRB_OK;
 }
@@ -450,16 +514,111 @@ extern "C" nsfrb_status nsfrb_search_destroy(nsfrb_search* h) {
   return NSFRB_OK;
 }
 
-static nsfrb_status launch_search(nsfrb_search* h, hipStream_t st) {
+static CubeDescHost cube_desc(const nsfrb_search* h, const void* z, int n_pix) {
   const nsfrb_search_config& c = h->cfg;
-  const void* z = h->d_z;
-  int n_pix = h->n_pix, n_sub = c.n_sub, n_t = c.n_time, n_dm = c.n_dm, rs = h->plan.rs;
-  void* args[] = {(void*)&z, (void*)&h->d_delays, (void*)&h->d_dmax, (void*)&h->d_norms,
-                  (void*)&n_pix, (void*)&n_sub, (void*)&n_t, (void*)&n_dm, (void*)&rs,
-                  (void*)&h->d_snr, (void*)&h->d_toa, (void*)&h->d_best_s, (void*)&h->d_best_d,
-                  (void*)&h->d_best_w, (void*)&h->d_best_t};
-  HIP_TRY(hipModuleLaunchKernel(h->search_fn, (unsigned)n_pix, 1, 1, kSearchThreads, 1, 1,
-                                (unsigned)h->plan.lds_bytes, st, args, nullptr));
+  CubeDescHost d{};
+  d.z = z;
+  d.delays = h->d_delays;
+  d.dmax = h->d_dmax;
+  d.norms = h->d_norms;
+  d.snr_max = h->d_snr;
+  d.toa = h->d_toa;
+  d.best_s = h->d_best_s;
+  d.best_d = h->d_best_d;
+  d.best_w = h->d_best_w;
+  d.best_t = h->d_best_t;
+  d.n_pix = n_pix;
+  d.n_sub = c.n_sub;
+  d.n_t = c.n_time;
+  d.n_dm = c.n_dm;
+  d.rs = h->rs;
+  d.cls = 0;
+  d.item_begin = 0;
+  return d;
+}
+
+static nsfrb_status launch_search_fn(const nsfrb_search* h, hipFunction_t fn, int pix, const void* z, int n_pix,
+                                     hipStream_t st) {
+  CubeDescHost d = cube_desc(h, z, n_pix);
+  void* args[] = {(void*)&d};
+  const unsigned n_items = (unsigned)((n_pix + pix - 1) / pix);
+  const size_t lds = lds_bytes_for(pix, h->cfg.n_sub, h->rs, h->cfg.store_dtype);
+  HIP_TRY(hipModuleLaunchKernel(fn, n_items, 1, 1, kSearchThreads, 1, 1, (unsigned)lds, st, args, nullptr));
+  return NSFRB_OK;
+}
+
+static nsfrb_status launch_search(const nsfrb_search* h, const void* z, hipStream_t st) {
+  return launch_search_fn(h, h->search_fn, h->pix, z, h->n_pix, st);
+}
+
+// Autotuner: time every pixels-per-workgroup candidate on this plan's shape
+// (the normalised-cube buffer, zeroed) and keep the fastest. Results are
+// cached per shape for the process. NSFRB_AUTOTUNE=0 keeps the heuristic
+// first candidate.
+struct TuneKey {
+  int C, n_sub, n_t, n_dm, n_pix_bucket, store;
+  std::vector<int32_t> widths;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(C, n_sub, n_t, n_dm, n_pix_bucket, store, widths) <
+           std::tie(o.C, o.n_sub, o.n_t, o.n_dm, o.n_pix_bucket, o.store, o.widths);
+  }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tune_cache;
+
+static nsfrb_status autotune(nsfrb_search* h, const std::vector<int>& pix) {
+  const nsfrb_search_config& c = h->cfg;
+  std::vector<hipFunction_t> fns(pix.size());
+  for (size_t i = 0; i < pix.size(); ++i)
+    HIP_TRY(hipModuleGetFunction(&fns[i], h->mod, single_kernel_name({h->C, pix[i]}).c_str()));
+  h->pix = pix[0];
+  h->search_fn = fns[0];
+  const char* env = std::getenv("NSFRB_AUTOTUNE");
+  if (pix.size() == 1 || (env && std::atoi(env) == 0)) return NSFRB_OK;
+  int bucket = 0;
+  while ((1 << bucket) < h->n_pix) ++bucket;
+  TuneKey key{h->C, c.n_sub, c.n_time, c.n_dm, bucket > 13 ? 13 : bucket, c.store_dtype, h->widths};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      for (size_t i = 0; i < pix.size(); ++i)
+        if (pix[i] == it->second) { h->pix = pix[i]; h->search_fn = fns[i]; }
+      return NSFRB_OK;
+    }
+  }
+  // time on up to 8192 pixels of a zeroed scratch cube (the cost per pixel does not depend on the data)
+  const int n_tune = h->n_pix < 8192 ? h->n_pix : 8192;
+  const size_t zbytes = (size_t)n_tune * c.n_sub * c.n_time * dtype_size(c.store_dtype);
+  void* zt = nullptr;
+  HIP_TRY(hipMalloc(&zt, zbytes));
+  std::unique_ptr<void, hipError_t (*)(void*)> zt_guard(zt, hipFree);
+  HIP_TRY(hipMemset(zt, 0, zbytes));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  for (size_t i = 0; i < pix.size(); ++i) {
+    nsfrb_status st = launch_search_fn(h, fns[i], pix[i], zt, n_tune, nullptr);   // warm-up
+    if (st != NSFRB_OK) return st;
+    HIP_TRY(hipEventRecord(e0, nullptr));
+    for (int r = 0; r < 3; ++r) {
+      st = launch_search_fn(h, fns[i], pix[i], zt, n_tune, nullptr);
+      if (st != NSFRB_OK) return st;
+    }
+    HIP_TRY(hipEventRecord(e1, nullptr));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    ms /= 3.f;
+    h->tuned_pix.push_back(pix[i]);
+    h->tuned_ms.push_back(ms);
+    if (ms < best_ms) { best_ms = ms; h->pix = pix[i]; h->search_fn = fns[i]; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = h->pix;
   return NSFRB_OK;
 }
 
@@ -472,11 +631,18 @@ extern "C" nsfrb_status nsfrb_search_run(nsfrb_search* h, const void* d_cube, vo
   HIP_TRY(hipSetDevice(h->device));
   const nsfrb_search_config& c = h->cfg;
   if (h->profiling) HIP_TRY(hipEventRecord(h->ev[0], st));
-  StatsLaunch sa{d_cube, c.n_time, c.n_sub, h->n_pix, c.norm, c.in_dtype, c.store_dtype,
-                 h->d_ext_med, h->d_ext_sig, h->d_med, h->d_sig, h->d_z, h->d_flags};
-  HIP_TRY(launch_stats(sa, st));
+  const void* z = d_cube;
+  if (c.layout == NSFRB_LAYOUT_TSP) {
+    StatsLaunch sa{d_cube, c.n_time, c.n_sub, h->n_pix, c.norm, c.in_dtype, c.store_dtype,
+                   h->d_ext_med, h->d_ext_sig, h->d_med, h->d_sig, h->d_z, h->d_flags};
+    HIP_TRY(launch_stats(sa, st));
+    z = h->d_z;
+  } else {
+    HIP_TRY(launch_zero_u64(h->d_flags, st));
+  }
+  h->last_z = z;
   if (h->profiling) HIP_TRY(hipEventRecord(h->ev[1], st));
-  nsfrb_status s2 = launch_search(h, st);
+  nsfrb_status s2 = launch_search(h, z, st);
   if (s2 != NSFRB_OK) return s2;
   if (h->profiling) HIP_TRY(hipEventRecord(h->ev[2], st));
   CandLaunch ca{h->d_best_s, h->d_best_d, h->d_best_w, h->d_best_t, h->n_pix, c.nx, c.max_candidates,
@@ -583,7 +749,7 @@ extern "C" nsfrb_status nsfrb_zcube_get(nsfrb_search* h, void* host_out) {
   if (st != NSFRB_OK) return st;
   if (!host_out) return fail(NSFRB_ERR_INVALID_ARG, "host_out is NULL");
   const size_t n = (size_t)h->n_pix * h->cfg.n_sub * h->cfg.n_time * dtype_size(h->cfg.store_dtype);
-  HIP_TRY(hipMemcpy(host_out, h->d_z, n, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(host_out, h->last_z, n, hipMemcpyDeviceToHost));
   return NSFRB_OK;
 }
 
@@ -610,5 +776,313 @@ extern "C" nsfrb_status nsfrb_stage_times_get(nsfrb_search* h, float* ms3) {
   if (st != NSFRB_OK) return st;
   if (!h->profiling) return fail(NSFRB_ERR_NOT_READY, "profiling was not enabled for the last run");
   for (int i = 0; i < 3; ++i) HIP_TRY(hipEventElapsedTime(&ms3[i], h->ev[i], h->ev[i + 1]));
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* info) {
+  g_last_error.clear();
+  if (!h || !info) return fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  info[0] = h->C;
+  info[1] = h->pix;
+  info[2] = h->rs;
+  info[3] = (int32_t)h->lds_bytes;
+  return NSFRB_OK;
+}
+
+// ------------------------------------------------------------------- batch
+struct nsfrb_batch {
+  std::vector<nsfrb_search*> cubes;
+  int device = 0, store = 0, nw = 0;
+  std::vector<KernelClass> classes;
+  std::vector<CubeDescHost> descs;        // item_begin / cls filled, z set per run
+  CubeDescHost* d_descs = nullptr;
+  long long n_items = 0;
+  unsigned grid = 0;
+  size_t lds = 0;
+  hipModule_t mod = nullptr;
+  hipFunction_t fn = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> graph_ptrs;    // cube pointers baked into the graph
+  bool use_graph = true, last_graph = false, ran = false;
+  hipEvent_t done = nullptr;
+};
+
+static void batch_release(nsfrb_batch* b) {
+  if (!b) return;
+  hipSetDevice(b->device);
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  if (b->d_descs) hipFree(b->d_descs);
+  if (b->done) hipEventDestroy(b->done);
+  for (auto* h : b->cubes) release(h);
+  delete b;
+}
+
+extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int32_t n_cubes, nsfrb_batch** out) {
+  g_last_error.clear();
+  if (!out || !cfgs || n_cubes < 1) return fail(NSFRB_ERR_INVALID_ARG, "need cfgs, n_cubes >= 1 and out");
+  *out = nullptr;
+  const nsfrb_search_config& c0 = cfgs[0];
+  for (int i = 0; i < n_cubes; ++i) {
+    const nsfrb_search_config& c = cfgs[i];
+    nsfrb_status st = validate(&c);
+    if (st != NSFRB_OK) return fail(st, "cube " + std::to_string(i) + ": " + g_last_error);
+    bool same = c.n_dm == c0.n_dm && c.n_width == c0.n_width && c.store_dtype == c0.store_dtype &&
+                c.in_dtype == c0.in_dtype && c.norm == c0.norm && c.layout == c0.layout && c.device == c0.device;
+    for (int d = 0; same && d < c.n_dm; ++d) same = c.dm[d] == c0.dm[d];
+    for (int w = 0; same && w < c.n_width; ++w) same = c.width[w] == c0.width[w];
+    if (!same) return fail(NSFRB_ERR_INVALID_ARG, "cube " + std::to_string(i) + " differs in DMs, widths, dtypes, "
+                                                  "normalisation, layout or device");
+  }
+  std::unique_ptr<nsfrb_batch, void (*)(nsfrb_batch*)> b(new nsfrb_batch, batch_release);
+  b->device = c0.device;
+  b->store = c0.store_dtype;
+  b->nw = c0.n_width;
+  for (int i = 0; i < n_cubes; ++i) {
+    nsfrb_search* h = nullptr;
+    nsfrb_status st = nsfrb_search_create(&cfgs[i], &h);
+    if (st != NSFRB_OK) return fail(st, "cube " + std::to_string(i) + ": " + g_last_error);
+    b->cubes.push_back(h);
+  }
+  // kernel classes: distinct (samples per lane, pixels per workgroup) of the cubes' tuned plans
+  long long items = 0;
+  for (auto* h : b->cubes) {
+    int cls = -1;
+    for (size_t k = 0; k < b->classes.size(); ++k)
+      if (b->classes[k].C == h->C && b->classes[k].PIX == h->pix) cls = (int)k;
+    if (cls < 0) { cls = (int)b->classes.size(); b->classes.push_back({h->C, h->pix}); }
+    CubeDescHost d = cube_desc(h, nullptr, h->n_pix);
+    d.cls = cls;
+    d.item_begin = items;
+    items += (h->n_pix + h->pix - 1) / h->pix;
+    b->descs.push_back(d);
+    b->lds = std::max(b->lds, lds_bytes_for(h->pix, h->cfg.n_sub, h->rs, h->cfg.store_dtype));
+  }
+  b->n_items = items;
+  std::string chain;
+  int npass = 1;
+  nsfrb_status st = gen_chain(b->cubes[0]->widths, chain, &npass);
+  if (st != NSFRB_OK) return st;
+  HIP_TRY(hipSetDevice(b->device));
+  st = load_module(b->device, gen_source(b->store, b->nw, npass, chain, {}, b->classes), &b->mod);
+  if (st != NSFRB_OK) return st;
+  HIP_TRY(hipModuleGetFunction(&b->fn, b->mod, "nsfrb_batch_kernel"));
+  int n_cu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, b->device));
+  const int per_cu = std::max(1, (int)(kLdsBudget / std::max<size_t>(b->lds, 1)));
+  const long long g = (long long)n_cu * std::min(per_cu, 2);
+  b->grid = (unsigned)std::max(1LL, std::min(g, b->n_items));
+  HIP_TRY(dalloc(&b->d_descs, b->descs.size()));
+  HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+  *out = b.release();
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_batch_destroy(nsfrb_batch* b) {
+  g_last_error.clear();
+  if (b && b->ran) {
+    hipSetDevice(b->device);
+    hipEventSynchronize(b->done);
+  }
+  batch_release(b);
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_batch_use_graph(nsfrb_batch* b, int32_t on) {
+  g_last_error.clear();
+  if (!b) return fail(NSFRB_ERR_INVALID_ARG, "batch is NULL");
+  b->use_graph = on != 0;
+  return NSFRB_OK;
+}
+
+// Statistics of every cube (or flag reset for search-layout input); sets last_z.
+static nsfrb_status batch_stats(nsfrb_batch* b, const void* const* d_cubes, hipStream_t st) {
+  for (size_t i = 0; i < b->cubes.size(); ++i) {
+    nsfrb_search* h = b->cubes[i];
+    const nsfrb_search_config& c = h->cfg;
+    if (c.layout == NSFRB_LAYOUT_TSP) {
+      StatsLaunch sa{d_cubes[i], c.n_time, c.n_sub, h->n_pix, c.norm, c.in_dtype, c.store_dtype,
+                     h->d_ext_med, h->d_ext_sig, h->d_med, h->d_sig, h->d_z, h->d_flags};
+      HIP_TRY(launch_stats(sa, st));
+      h->last_z = h->d_z;
+    } else {
+      HIP_TRY(launch_zero_u64(h->d_flags, st));
+      h->last_z = d_cubes[i];
+    }
+  }
+  return NSFRB_OK;
+}
+
+static nsfrb_status batch_candidates(nsfrb_batch* b, hipStream_t st) {
+  for (auto* h : b->cubes) {
+    const nsfrb_search_config& c = h->cfg;
+    CandLaunch ca{h->d_best_s, h->d_best_d, h->d_best_w, h->d_best_t, h->n_pix, c.nx, c.max_candidates,
+                  c.snr_threshold, h->d_keys, h->d_count, h->d_cands, h->d_nout};
+    HIP_TRY(launch_candidates(ca, st));
+    HIP_TRY(hipMemcpyAsync(h->h_nout, h->d_nout, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h->h_cands, h->d_cands, sizeof(nsfrb_candidate) * c.max_candidates,
+                           hipMemcpyDeviceToHost, st));
+  }
+  return NSFRB_OK;
+}
+
+static nsfrb_status batch_enqueue(nsfrb_batch* b, const void* const* d_cubes, hipStream_t st) {
+  nsfrb_status s = batch_stats(b, d_cubes, st);
+  if (s != NSFRB_OK) return s;
+  void* args[] = {(void*)&b->d_descs, nullptr, nullptr};
+  int n = (int)b->cubes.size();
+  long long items = b->n_items;
+  args[1] = &n;
+  args[2] = &items;
+  HIP_TRY(hipModuleLaunchKernel(b->fn, b->grid, 1, 1, kSearchThreads, 1, 1, (unsigned)b->lds, st, args, nullptr));
+  return batch_candidates(b, st);
+}
+
+extern "C" nsfrb_status nsfrb_batch_run(nsfrb_batch* b, const void* const* d_cubes, void* stream) {
+  g_last_error.clear();
+  if (!b || !d_cubes) return fail(NSFRB_ERR_INVALID_ARG, "batch and d_cubes must be non-NULL");
+  for (size_t i = 0; i < b->cubes.size(); ++i)
+    if (!d_cubes[i]) return fail(NSFRB_ERR_INVALID_ARG, "a cube pointer is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(b->device));
+  std::vector<const void*> ptrs(d_cubes, d_cubes + b->cubes.size());
+  // descriptors carry the normalised-cube pointers; refresh them when the inputs change
+  const bool changed = ptrs != b->graph_ptrs;
+  if (changed || !b->ran) {
+    if (b->ran) HIP_TRY(hipEventSynchronize(b->done));
+    for (size_t i = 0; i < b->cubes.size(); ++i) {
+      nsfrb_search* h = b->cubes[i];
+      b->descs[i].z = h->cfg.layout == NSFRB_LAYOUT_TSP ? h->d_z : d_cubes[i];
+    }
+    HIP_TRY(hipMemcpy(b->d_descs, b->descs.data(), b->descs.size() * sizeof(CubeDescHost), hipMemcpyHostToDevice));
+  }
+  if (!b->use_graph) {
+    nsfrb_status s = batch_enqueue(b, d_cubes, st);
+    if (s != NSFRB_OK) return s;
+    b->last_graph = false;
+    b->graph_ptrs = ptrs;
+  } else {
+    if (changed || !b->exec) {
+      if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+      if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+      HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+      nsfrb_status s = batch_enqueue(b, d_cubes, b->cap_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+      if (s != NSFRB_OK) { if (g) hipGraphDestroy(g); return s; }
+      HIP_TRY(e);
+      b->graph = g;
+      HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+      b->graph_ptrs = ptrs;
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, st));
+    b->last_graph = true;
+  }
+  HIP_TRY(hipEventRecord(b->done, st));
+  for (auto* h : b->cubes) h->ran = true;
+  b->ran = true;
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_batch_run_separate(nsfrb_batch* b, const void* const* d_cubes, void* stream) {
+  g_last_error.clear();
+  if (!b || !d_cubes) return fail(NSFRB_ERR_INVALID_ARG, "batch and d_cubes must be non-NULL");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(b->device));
+  nsfrb_status s = batch_stats(b, d_cubes, st);
+  if (s != NSFRB_OK) return s;
+  for (auto* h : b->cubes) {
+    s = launch_search(h, h->last_z, st);
+    if (s != NSFRB_OK) return s;
+  }
+  s = batch_candidates(b, st);
+  if (s != NSFRB_OK) return s;
+  HIP_TRY(hipEventRecord(b->done, st));
+  for (auto* h : b->cubes) h->ran = true;
+  b->ran = true;
+  b->last_graph = false;
+  return NSFRB_OK;
+}
+
+static nsfrb_status batch_cube(nsfrb_batch* b, int32_t cube, nsfrb_search** h) {
+  if (!b) return fail(NSFRB_ERR_INVALID_ARG, "batch is NULL");
+  if (cube < 0 || cube >= (int)b->cubes.size()) return fail(NSFRB_ERR_INVALID_ARG, "cube index out of range");
+  if (!b->ran) return fail(NSFRB_ERR_NOT_READY, "no run has been enqueued on this batch");
+  HIP_TRY(hipSetDevice(b->device));
+  HIP_TRY(hipEventSynchronize(b->done));
+  *h = b->cubes[cube];
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_batch_candidates_get(nsfrb_batch* b, int32_t cube, nsfrb_candidate* host_out,
+                                                   int32_t capacity, int32_t* n_written, int32_t* n_total) {
+  g_last_error.clear();
+  nsfrb_search* h = nullptr;
+  nsfrb_status st = batch_cube(b, cube, &h);
+  if (st != NSFRB_OK) return st;
+  return nsfrb_candidates_get(h, host_out, capacity, n_written, n_total);
+}
+
+extern "C" nsfrb_status nsfrb_batch_maps_get(nsfrb_batch* b, int32_t cube, float* snr_max, int32_t* toa) {
+  g_last_error.clear();
+  nsfrb_search* h = nullptr;
+  nsfrb_status st = batch_cube(b, cube, &h);
+  if (st != NSFRB_OK) return st;
+  return nsfrb_maps_get(h, snr_max, toa);
+}
+
+extern "C" nsfrb_status nsfrb_batch_info_get(nsfrb_batch* b, int64_t* info) {
+  g_last_error.clear();
+  if (!b || !info) return fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  info[0] = b->n_items;
+  info[1] = b->grid;
+  info[2] = (int64_t)b->lds;
+  info[3] = (int64_t)b->classes.size();
+  info[4] = b->last_graph ? 1 : 0;
+  return NSFRB_OK;
+}
+
+// --------------------------------------------------------------- generator
+static size_t elem_count(int32_t n_pix, int32_t n_sub, int32_t n_time) {
+  return (size_t)n_pix * n_sub * n_time;
+}
+
+extern "C" nsfrb_status nsfrb_generate_noise(void* d_out, int32_t dtype, int32_t layout, int32_t n_pix,
+                                             int32_t n_sub, int32_t n_time, uint64_t seed, float sigma,
+                                             void* stream) {
+  g_last_error.clear();
+  if (!d_out || dtype < 0 || dtype > 2 || (layout != 0 && layout != 1) || n_pix < 1 || n_sub < 1 || n_time < 1 ||
+      !std::isfinite(sigma))
+    return fail(NSFRB_ERR_INVALID_ARG, "bad generator arguments");
+  HIP_TRY(launch_noise(d_out, dtype, (long long)elem_count(n_pix, n_sub, n_time), seed, sigma, (hipStream_t)stream));
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_inject_boxcar(void* d_cube, int32_t dtype, int32_t layout, int32_t n_pix,
+                                            int32_t n_sub, int32_t n_time, int32_t pixel, int32_t t0,
+                                            int32_t width, float amp, const int32_t* host_offsets, void* stream) {
+  g_last_error.clear();
+  if (!d_cube || !host_offsets || dtype < 0 || dtype > 2 || (layout != 0 && layout != 1) || n_pix < 1 ||
+      n_sub < 1 || n_time < 1 || pixel < 0 || pixel >= n_pix || width < 1 || !std::isfinite(amp))
+    return fail(NSFRB_ERR_INVALID_ARG, "bad injection arguments");
+  // a utility for building inputs: synchronous, so the host offsets can be released on return
+  int* d_off = nullptr;
+  HIP_TRY(hipMalloc((void**)&d_off, sizeof(int) * n_sub));
+  std::unique_ptr<void, hipError_t (*)(void*)> guard(d_off, hipFree);
+  HIP_TRY(hipMemcpy(d_off, host_offsets, sizeof(int) * n_sub, hipMemcpyHostToDevice));
+  HIP_TRY(launch_inject(d_cube, dtype, layout, n_pix, n_sub, n_time, pixel, t0, width, amp, d_off,
+                        (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_philox_fill(uint32_t* d_out, int64_t n_blocks, uint64_t seed, void* stream) {
+  g_last_error.clear();
+  if (!d_out || n_blocks < 0) return fail(NSFRB_ERR_INVALID_ARG, "bad arguments");
+  HIP_TRY(launch_philox_fill(d_out, n_blocks, seed, (hipStream_t)stream));
   return NSFRB_OK;
 }

@@ -19,6 +19,7 @@ struct StatsLaunch {
   unsigned long long* flag_count;
 };
 hipError_t launch_stats(const StatsLaunch& a, hipStream_t st);
+hipError_t launch_zero_u64(unsigned long long* p, hipStream_t st);
 
 struct CandLaunch {
   const float* best_snr;
@@ -34,4 +35,32 @@ struct CandLaunch {
 };
 hipError_t launch_candidates(const CandLaunch& a, hipStream_t st);
 
+}  // namespace nsfrb
+
+namespace nsfrb {
+
+// Host mirror of the device CubeDesc (same field order and types).
+struct CubeDescHost {
+  const void* z;
+  const int* delays;
+  const int* dmax;
+  const float* norms;
+  float* snr_max;
+  int* toa;
+  float* best_s;
+  int* best_d;
+  int* best_w;
+  int* best_t;
+  int n_pix, n_sub, n_t, n_dm, rs, cls;
+  long long item_begin;
+};
+static_assert(sizeof(CubeDescHost) == 112, "CubeDesc layout");
+
+}  // namespace nsfrb
+
+namespace nsfrb {
+hipError_t launch_philox_fill(uint32_t* out, long long n_blocks, unsigned long long seed, hipStream_t st);
+hipError_t launch_noise(void* out, int dtype, long long n, unsigned long long seed, float sigma, hipStream_t st);
+hipError_t launch_inject(void* cube, int dtype, int layout, int n_pix, int n_sub, int n_t, int pixel, int t0,
+                         int width, float amp, const int* d_offsets, hipStream_t st);
 }  // namespace nsfrb

@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY",
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 DTYPE_BYTES = {"f32": 4, "f16": 2, "bf16": 2}
 NORMS = {"pixel_subband": 0, "pixel": 1, "external": 2, "none": 3}
+LAYOUTS = {"tsp": 0, "pst": 1}
 
 # every symbol declared in include/nsfrb.h
 EXPORTS = [
@@ -26,7 +27,10 @@ EXPORTS = [
     "nsfrb_search_create", "nsfrb_search_destroy", "nsfrb_search_run", "nsfrb_candidates_get",
     "nsfrb_delay_table_get", "nsfrb_maps_get", "nsfrb_best_get", "nsfrb_noise_stats_get",
     "nsfrb_noise_stats_set", "nsfrb_zcube_get", "nsfrb_flag_count_get", "nsfrb_maps_device",
-    "nsfrb_profiling_enable", "nsfrb_stage_times_get",
+    "nsfrb_profiling_enable", "nsfrb_stage_times_get", "nsfrb_search_plan_info",
+    "nsfrb_batch_create", "nsfrb_batch_destroy", "nsfrb_batch_run", "nsfrb_batch_run_separate",
+    "nsfrb_batch_use_graph", "nsfrb_batch_candidates_get", "nsfrb_batch_maps_get", "nsfrb_batch_info_get",
+    "nsfrb_generate_noise", "nsfrb_inject_boxcar", "nsfrb_philox_fill",
 ]
 
 
@@ -41,7 +45,7 @@ class Config(ctypes.Structure):
         ("n_width", ctypes.c_int32), ("width", ctypes.POINTER(ctypes.c_int32)),
         ("in_dtype", ctypes.c_int32), ("store_dtype", ctypes.c_int32), ("norm", ctypes.c_int32),
         ("snr_threshold", ctypes.c_float), ("max_candidates", ctypes.c_int32),
-        ("device", ctypes.c_int32),
+        ("device", ctypes.c_int32), ("layout", ctypes.c_int32),
     ]
 
 
@@ -88,6 +92,20 @@ def lib():
             "nsfrb_profiling_enable": ([vp, i32], ctypes.c_int),
             "nsfrb_stage_times_get": ([vp, pf], ctypes.c_int),
             "nsfrb_debug_plan_source": ([ctypes.POINTER(Config), ctypes.c_char_p, i32, i32], ctypes.c_int),
+            "nsfrb_search_plan_info": ([vp, pi32], ctypes.c_int),
+            "nsfrb_batch_create": ([ctypes.POINTER(Config), i32, ctypes.POINTER(vp)], ctypes.c_int),
+            "nsfrb_batch_destroy": ([vp], ctypes.c_int),
+            "nsfrb_batch_run": ([vp, ctypes.POINTER(vp), vp], ctypes.c_int),
+            "nsfrb_batch_run_separate": ([vp, ctypes.POINTER(vp), vp], ctypes.c_int),
+            "nsfrb_batch_use_graph": ([vp, i32], ctypes.c_int),
+            "nsfrb_batch_candidates_get": ([vp, i32, ctypes.POINTER(Candidate), i32, pi32, pi32], ctypes.c_int),
+            "nsfrb_batch_maps_get": ([vp, i32, pf, pi32], ctypes.c_int),
+            "nsfrb_batch_info_get": ([vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+            "nsfrb_generate_noise": ([vp, i32, i32, i32, i32, i32, ctypes.c_uint64, ctypes.c_float, vp],
+                                     ctypes.c_int),
+            "nsfrb_inject_boxcar": ([vp, i32, i32, i32, i32, i32, i32, i32, i32, ctypes.c_float, pi32, vp],
+                                    ctypes.c_int),
+            "nsfrb_philox_fill": ([vp, ctypes.c_int64, ctypes.c_uint64, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -115,13 +133,13 @@ class SearchConfig:
 
     def __init__(self, nx, ny, n_time, freqs_ghz, dms, widths, f_ref_ghz=None, dt_ms=134.2,
                  k_dm_ms=4.15, in_dtype="f32", store_dtype="f32", norm="pixel_subband",
-                 snr_threshold=6.0, max_candidates=10, device=0):
+                 snr_threshold=6.0, max_candidates=10, device=0, layout="tsp"):
         self.freqs = np.ascontiguousarray(freqs_ghz, dtype=np.float64)
         self.dms = np.ascontiguousarray(dms, dtype=np.float64)
         self.widths = np.ascontiguousarray(widths, dtype=np.int32)
         self.nx, self.ny, self.n_time = int(nx), int(ny), int(n_time)
         self.n_sub = int(self.freqs.size)
-        self.in_dtype, self.store_dtype, self.norm = in_dtype, store_dtype, norm
+        self.in_dtype, self.store_dtype, self.norm, self.layout = in_dtype, store_dtype, norm, layout
         self.max_candidates = int(max_candidates)
         c = Config()
         c.struct_size = ctypes.sizeof(Config)
@@ -135,6 +153,7 @@ class SearchConfig:
         c.snr_threshold = float(snr_threshold)
         c.max_candidates = self.max_candidates
         c.device = int(device)
+        c.layout = LAYOUTS[layout]
         self.c = c
 
     @property
@@ -261,3 +280,92 @@ class Search:
         out = np.zeros((self.cfg.dms.size, self.cfg.n_sub), np.int32)
         check(lib().nsfrb_delay_table_get(self.h, _ptr(out, ctypes.c_int32)))
         return out
+
+    def plan_info(self):
+        out = np.zeros(4, np.int32)
+        check(lib().nsfrb_search_plan_info(self.h, _ptr(out, ctypes.c_int32)))
+        return dict(samples_per_lane=int(out[0]), pixels_per_workgroup=int(out[1]), row_len=int(out[2]),
+                    lds_bytes=int(out[3]))
+
+
+class Batch:
+    """Many uneven cubes searched by one persistent, graph-captured launch."""
+
+    def __init__(self, cfgs):
+        self.cfgs = list(cfgs)
+        arr = (Config * len(self.cfgs))(*[c.c for c in self.cfgs])
+        self._arr = arr
+        h = ctypes.c_void_p()
+        check(lib().nsfrb_batch_create(arr, len(self.cfgs), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nsfrb_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _ptrs(self, ptrs):
+        return (ctypes.c_void_p * len(ptrs))(*[ctypes.c_void_p(int(p)) for p in ptrs])
+
+    def run(self, ptrs, stream=0):
+        check(lib().nsfrb_batch_run(self.h, self._ptrs(ptrs), ctypes.c_void_p(int(stream))))
+
+    def run_separate(self, ptrs, stream=0):
+        check(lib().nsfrb_batch_run_separate(self.h, self._ptrs(ptrs), ctypes.c_void_p(int(stream))))
+
+    def use_graph(self, on=True):
+        check(lib().nsfrb_batch_use_graph(self.h, 1 if on else 0))
+
+    def candidates(self, i):
+        cap = self.cfgs[i].max_candidates
+        arr = (Candidate * cap)()
+        nw, nt = ctypes.c_int32(), ctypes.c_int32()
+        st = lib().nsfrb_batch_candidates_get(self.h, i, arr, cap, ctypes.byref(nw), ctypes.byref(nt))
+        if st not in (OK, TRUNCATED):
+            check(st)
+        return [dict(x=c.x, y=c.y, dm_index=c.dm_index, width_index=c.width_index, toa=c.toa, snr=c.snr)
+                for c in arr[:nw.value]], nt.value
+
+    def maps(self, i):
+        c = self.cfgs[i]
+        shape = (c.dms.size, c.widths.size, c.n_pix)
+        snr = np.zeros(shape, np.float32)
+        toa = np.zeros(shape, np.int32)
+        check(lib().nsfrb_batch_maps_get(self.h, i, _ptr(snr, ctypes.c_float), _ptr(toa, ctypes.c_int32)))
+        return snr, toa
+
+    def info(self):
+        out = np.zeros(5, np.int64)
+        check(lib().nsfrb_batch_info_get(self.h, _ptr(out, ctypes.c_int64)))
+        return dict(work_items=int(out[0]), grid=int(out[1]), lds_bytes=int(out[2]), classes=int(out[3]),
+                    graph=bool(out[4]))
+
+
+def generate_noise(d_ptr, dtype, layout, n_pix, n_sub, n_time, seed, sigma=1.0, stream=0):
+    check(lib().nsfrb_generate_noise(ctypes.c_void_p(int(d_ptr)), DTYPES[dtype], LAYOUTS[layout], n_pix, n_sub,
+                                     n_time, ctypes.c_uint64(seed), float(sigma), ctypes.c_void_p(int(stream))))
+
+
+def inject_boxcar(d_ptr, dtype, layout, n_pix, n_sub, n_time, pixel, t0, width, amp, offsets, stream=0):
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    assert off.size == n_sub
+    check(lib().nsfrb_inject_boxcar(ctypes.c_void_p(int(d_ptr)), DTYPES[dtype], LAYOUTS[layout], n_pix, n_sub,
+                                    n_time, int(pixel), int(t0), int(width), float(amp), _ptr(off, ctypes.c_int32),
+                                    ctypes.c_void_p(int(stream))))
+
+
+def philox_fill(d_ptr, n_blocks, seed, stream=0):
+    check(lib().nsfrb_philox_fill(ctypes.c_void_p(int(d_ptr)), int(n_blocks), ctypes.c_uint64(seed),
+                                  ctypes.c_void_p(int(stream))))

@@ -139,3 +139,54 @@ def config2(seed=2, nx=256, ny=256, nt=2048, ns=16, n_pulses=100, n_spikes=20,
                 dms=np.linspace(0.0, dm_max, n_dm), widths=widths_pow2(1024, (1200,)),
                 theta=6.0, sigma_pix=sig, injections=inj, spikes=spikes, stripes=stripes)
     return cube, meta
+
+
+# ------------------------------------------------------ counter-based RNG
+PHILOX_M0, PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+PHILOX_W0, PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+
+
+def philox4x32_10(counters, key):
+    """Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): counters [N,4] uint32, key (k0, k1).
+
+    Each round multiplies words 0 and 2 by the two multipliers (32x32 -> 64
+    bits); the new words are (hi(M1*x2) ^ x1 ^ k0, lo(M1*x2), hi(M0*x0) ^ x3 ^ k1,
+    lo(M0*x0)); the key is bumped by the Weyl constants between rounds.
+    """
+    x = np.asarray(counters, dtype=np.uint64).reshape(-1, 4).copy()
+    k0, k1 = np.uint64(key[0] & 0xFFFFFFFF), np.uint64(key[1] & 0xFFFFFFFF)
+    mask = np.uint64(0xFFFFFFFF)
+    for r in range(10):
+        if r:
+            k0 = (k0 + np.uint64(PHILOX_W0)) & mask
+            k1 = (k1 + np.uint64(PHILOX_W1)) & mask
+        p0 = np.uint64(PHILOX_M0) * x[:, 0]
+        p1 = np.uint64(PHILOX_M1) * x[:, 2]
+        n = np.empty_like(x)
+        n[:, 0] = (p1 >> np.uint64(32)) ^ x[:, 1] ^ k0
+        n[:, 1] = p1 & mask
+        n[:, 2] = (p0 >> np.uint64(32)) ^ x[:, 3] ^ k1
+        n[:, 3] = p0 & mask
+        x = n
+    return x.astype(np.uint32)
+
+
+def philox_blocks(n_blocks, seed):
+    """Words of blocks 0..n-1: counter (i, 0, 0, 0), key (seed low, seed high)."""
+    i = np.arange(n_blocks, dtype=np.uint64)
+    c = np.zeros((n_blocks, 4), dtype=np.uint64)
+    c[:, 0] = i & np.uint64(0xFFFFFFFF)
+    c[:, 1] = i >> np.uint64(32)
+    return philox4x32_10(c, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)).reshape(-1)
+
+
+def philox_normals(n, seed, sigma=1.0):
+    """Box-Muller normals from Philox blocks, in FP64 (reference for the device generator)."""
+    w = philox_blocks((n + 3) // 4, seed).astype(np.float64).reshape(-1, 4)
+    u = lambda a: (np.floor(a / 256.0) + 0.5) / 16777216.0
+    r0 = np.sqrt(-2.0 * np.log(u(w[:, 0])))
+    a0 = 2 * np.pi * u(w[:, 1])
+    r1 = np.sqrt(-2.0 * np.log(u(w[:, 2])))
+    a1 = 2 * np.pi * u(w[:, 3])
+    v = np.stack([r0 * np.cos(a0), r0 * np.sin(a0), r1 * np.cos(a1), r1 * np.sin(a1)], axis=1).reshape(-1)
+    return sigma * v[:n]

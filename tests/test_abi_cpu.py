@@ -99,14 +99,14 @@ def test_forced_allocation_failure(L, monkeypatch):
 
 def test_chain_plan_composes_non_power_of_two_widths(L):
     src = c2_config().plan_source()
-    assert "constexpr int kC = 33;" in src
+    assert "nsfrb_search_c33_p1" in src and "search_group<33, 1>" in src
     # 1200 = 16 + 32 + 128 + 1024 placed end to end: offsets 16, 48, 176
     for frag in ("copy_arr(acc0, a0)", "shift_add<16>(acc0", "shift_add<48>(acc0", "shift_add<176>(acc0",
                  "rep(11, acc0)"):
         assert frag in src
     src = nsfrb.SearchConfig(4, 4, 100, [1.3, 1.4], [0.0], [3, 200, 7, 64]).plan_source()
-    assert "rep.invalid(1)" in src          # 200 > n_time
     assert "rep(3, a0)" in src             # 64 = level 6 (even level -> a0)
+    assert "rep(1, acc" in src             # 200 > n_time is still formed; its windows all reach -inf
 
 
 @pytest.mark.parametrize("store", ["f32", "f16", "bf16"])
@@ -118,7 +118,18 @@ def test_search_kernel_compiles_for_gfx950(L, store):
     c1.plan_source(compile=True)
 
 
-def test_too_many_open_accumulators_is_unsupported(L):
-    c = nsfrb.SearchConfig(4, 4, 1024, [1.3, 1.4], [0.0], [1023, 1021, 1019, 1017])
-    with pytest.raises(nsfrb.NsfrbError):
-        c.plan_source()
+def test_many_open_accumulators_split_into_passes(L):
+    c = nsfrb.SearchConfig(4, 4, 1024, [1.3, 1.4], [0.0], [1023, 1021, 1019, 1017, 1, 64, 5])
+    src = c.plan_source(compile=True)
+    assert "#define NSFRB_NPASS 2" in src
+    for iw in range(7):
+        assert src.count(f"rep({iw}, ") == 1
+
+
+def test_pst_layout_rules(L):
+    ok = c2_config(layout="pst", norm="none", in_dtype="f16", store_dtype="f16")
+    assert ok.validate() == nsfrb.OK
+    bad = c2_config(layout="pst", norm="none", in_dtype="f32", store_dtype="f16")
+    assert bad.validate() == nsfrb.INVALID_ARG
+    bad = c2_config(layout="pst")
+    assert bad.validate() == nsfrb.INVALID_ARG

@@ -1,0 +1,140 @@
+"""GPU tests of the batched search and the device generator (needs an MI355X).
+
+* the persistent, graph-captured batch gives results bitwise equal to one plain
+  launch per cube, on every graph replay (with eager work in between);
+* on small host-generated cubes the batch matches the FP64 oracle;
+* the device Philox4x32-10 words equal the host implementation bit for bit,
+  and its Box-Muller normals agree with an FP64 evaluation.
+"""
+import numpy as np
+import pytest
+
+from oracle.delays import delay_table
+from paper_2510_18136_amd import nsfrb, synth
+from tests._lib import ensure_built
+from tests.test_gpu_search import compare, oracle_run, to_device
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+C1_DMS = np.linspace(0, 1000, 8)
+C1_W = [1, 2, 4, 8, 16]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    ensure_built()
+    assert torch.cuda.is_available()
+
+
+def test_philox_words_match_host():
+    n = 50_000
+    out = torch.zeros(4 * n, dtype=torch.int32, device="cuda")
+    print("[gpu] philox fill", flush=True)
+    nsfrb.philox_fill(out.data_ptr(), n, 0x123456789ABCDEF, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    dev = out.cpu().numpy().view(np.uint32)
+    assert np.array_equal(dev, synth.philox_blocks(n, 0x123456789ABCDEF))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_device_noise_matches_fp64_box_muller(dtype):
+    n = 1 << 20
+    tdt = torch.float32 if dtype == "f32" else torch.float16
+    out = torch.empty(n, dtype=tdt, device="cuda")
+    nsfrb.generate_noise(out.data_ptr(), dtype, "pst", n, 1, 1, seed=77, sigma=1.5,
+                         stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    got = out.float().cpu().numpy().astype(np.float64)
+    ref = synth.philox_normals(n, 77, sigma=1.5)
+    tol = 1e-5 * np.maximum(1, np.abs(ref)) if dtype == "f32" else 2e-3 * np.maximum(1, np.abs(ref))
+    assert (np.abs(got - ref) <= tol).all()
+    assert abs(got.mean()) < 0.01 and abs(got.std() - 1.5) < 0.01
+
+
+def uneven_cfgs(rng, n, layout, store):
+    cfgs = []
+    for i in range(n):
+        side = int(rng.choice([8, 16, 24, 40]))
+        ns = int(rng.choice([8, 16]))
+        nt = int(rng.choice([64, 100, 256, 300, 600]))
+        cfgs.append(nsfrb.SearchConfig(side, side, nt, np.linspace(1.311, 1.499, ns), C1_DMS, C1_W,
+                                       in_dtype=store, store_dtype=store,
+                                       norm="none" if layout == "pst" else "pixel_subband",
+                                       layout=layout, snr_threshold=5.0, max_candidates=16))
+    return cfgs
+
+
+def results(b, n):
+    out = []
+    for i in range(n):
+        snr, toa = b.maps(i)
+        cands, ntot = b.candidates(i)
+        out.append((snr, toa, cands, ntot))
+    return out
+
+
+def same(a, b):
+    for (s1, t1, c1, n1), (s2, t2, c2, n2) in zip(a, b):
+        assert np.array_equal(s1, s2, equal_nan=True) and np.array_equal(t1, t2)
+        assert c1 == c2 and n1 == n2
+
+
+def test_batch_graph_replays_equal_separate_launches():
+    rng = np.random.default_rng(4)
+    cfgs = uneven_cfgs(rng, 9, "pst", "f16")
+    stream = torch.cuda.current_stream()
+    cubes = []
+    for i, c in enumerate(cfgs):
+        x = torch.empty(c.n_pix * c.n_sub * c.n_time, dtype=torch.float16, device="cuda")
+        nsfrb.generate_noise(x.data_ptr(), "f16", "pst", c.n_pix, c.n_sub, c.n_time, seed=1000 + i,
+                             stream=stream.cuda_stream)
+        off = delay_table(c.freqs, c.freqs.max(), 134.2, [500.0])[0]
+        nsfrb.inject_boxcar(x.data_ptr(), "f16", "pst", c.n_pix, c.n_sub, c.n_time, pixel=c.n_pix // 2, t0=20,
+                            width=4, amp=3.0, offsets=off, stream=stream.cuda_stream)
+        cubes.append(x)
+    ptrs = [x.data_ptr() for x in cubes]
+    print(f"[gpu] batch of {len(cfgs)} cubes", flush=True)
+    with nsfrb.Batch(cfgs) as b:
+        b.run_separate(ptrs, stream.cuda_stream)
+        ref = results(b, len(cfgs))
+        for rep in range(3):
+            junk = torch.randn(1 << 20, device="cuda").sum().item()          # eager work between replays
+            b.run(ptrs, stream.cuda_stream)
+            got = results(b, len(cfgs))
+            assert b.info()["graph"]
+            same(got, ref)
+        b.use_graph(False)
+        b.run(ptrs, stream.cuda_stream)
+        same(results(b, len(cfgs)), ref)
+        info = b.info()
+        assert info["work_items"] > 0 and info["classes"] >= 1
+    # every cube's pulse is found at its pixel
+    for i, (snr, toa, cands, ntot) in enumerate(ref):
+        assert ntot >= 1 and cands[0]["x"] + cfgs[i].nx * cands[0]["y"] == cfgs[i].n_pix // 2
+
+
+def test_batch_matches_oracle_on_small_cubes():
+    rng = np.random.default_rng(8)
+    cfgs = uneven_cfgs(rng, 5, "tsp", "f32")
+    stream = torch.cuda.current_stream()
+    host, dev = [], []
+    for i, c in enumerate(cfgs):
+        cube = synth.noise_cube(c.n_time, c.n_sub, c.n_pix, seed=50 + i)
+        off = delay_table(c.freqs, c.freqs.max(), 134.2, [428.0])[0]
+        synth.inject_boxcar(cube, 3, 30, off, 8, 2.5)
+        host.append(cube)
+        dev.append(to_device(cube, "f32"))
+    with nsfrb.Batch(cfgs) as b:
+        print("[gpu] batch vs oracle", flush=True)
+        b.run([x.data_ptr() for x in dev], stream.cuda_stream)
+        for i, c in enumerate(cfgs):
+            snr, toa = b.maps(i)
+            cands, ntot = b.candidates(i)
+            o = oracle_run(host[i], c)
+            fin = np.isfinite(o["snr_max"])
+            assert np.array_equal(np.isfinite(snr), fin)
+            assert np.abs(snr[fin] - o["snr_max"][fin]).max() <= 1e-4
+            clear = fin & (o["margin"] > 2e-4)
+            assert np.array_equal(toa[clear], o["toa"][clear])
+            assert ntot == o["n_total"]

@@ -107,7 +107,7 @@ def compare(g, o, cfg, tol=TOL, eps=EPS, exact_z=True):
     np.testing.assert_array_equal(g["best_d"][clear_p], o["best_d"][clear_p])
     np.testing.assert_array_equal(g["best_w"][clear_p], o["best_w"][clear_p])
     ok_t = clear_p & (o["margin"][o["best_d"].clip(0), o["best_w"].clip(0), np.arange(o["best"].size)] > eps)
-    np.testing.assert_array_equal(g["best_t"][ok_t], o["best_t"][ok_t])
+    np.testing.assert_array_equal(g["best_t"][ok_t], o["best_toa"][ok_t])
     assert np.abs(g["best"][okp] - o["best"][okp]).max(initial=0.0) <= tol
     # candidates: total count, then the ranked list where it is unambiguous
     theta = float(cfg.c.snr_threshold)
