@@ -41,8 +41,9 @@ __global__ void k_philox_fill(uint32_t* __restrict__ out, long long n_blocks, ui
   }
 }
 
-// uniform in (0, 1): top 24 bits, centred in their interval
-__device__ __forceinline__ float unit_open(uint32_t u) { return ((float)(u >> 8) + 0.5f) * (1.0f / 16777216.0f); }
+// uniform in (0, 1): top 23 bits, centred in their interval (exact in FP32,
+// so the value never rounds to 1)
+__device__ __forceinline__ float unit_open(uint32_t u) { return ((float)(u >> 9) + 0.5f) * (1.0f / 8388608.0f); }
 
 template <typename T>
 __global__ void k_noise(T* __restrict__ out, long long n, uint32_t k0, uint32_t k1, float sigma) {

@@ -183,7 +183,7 @@ def philox_blocks(n_blocks, seed):
 def philox_normals(n, seed, sigma=1.0):
     """Box-Muller normals from Philox blocks, in FP64 (reference for the device generator)."""
     w = philox_blocks((n + 3) // 4, seed).astype(np.float64).reshape(-1, 4)
-    u = lambda a: (np.floor(a / 256.0) + 0.5) / 16777216.0
+    u = lambda a: (np.floor(a / 512.0) + 0.5) / 8388608.0
     r0 = np.sqrt(-2.0 * np.log(u(w[:, 0])))
     a0 = 2 * np.pi * u(w[:, 1])
     r1 = np.sqrt(-2.0 * np.log(u(w[:, 2])))

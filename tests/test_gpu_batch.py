@@ -47,7 +47,7 @@ def test_device_noise_matches_fp64_box_muller(dtype):
     torch.cuda.synchronize()
     got = out.float().cpu().numpy().astype(np.float64)
     ref = synth.philox_normals(n, 77, sigma=1.5)
-    tol = 1e-5 * np.maximum(1, np.abs(ref)) if dtype == "f32" else 2e-3 * np.maximum(1, np.abs(ref))
+    tol = 5e-5 * np.maximum(1, np.abs(ref)) if dtype == "f32" else 2e-3 * np.maximum(1, np.abs(ref))
     assert (np.abs(got - ref) <= tol).all()
     assert abs(got.mean()) < 0.01 and abs(got.std() - 1.5) < 0.01
 
