@@ -37,18 +37,21 @@ namespace nsfrb {
 constexpr int kWaves = 8;
 constexpr float kNegInf = -__builtin_inff();
 
-// Value of x held by lane l+1 (lane 63 gets -inf).
+// Value of x held by lane l+1 (lane 63 reads 0). Only used where the sum it
+// feeds is already -inf for lane 63 (see shift_add).
 __device__ __forceinline__ float lane_next(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(kNegInf), __float_as_int(x),
-                                                    0x130 /* wave_shl:1 */, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130 /* wave_shl:1 */, 0xf, 0xf, true));
 }
-// Value of x held by lane l+q, q >= 2 (-inf beyond lane 63).
+// Value of x held by lane (l+q) mod 64, q >= 2.
 __device__ __forceinline__ float lane_ahead(float x, int q, int l) {
-  const int v = __builtin_amdgcn_ds_bpermute((l + q) << 2, __float_as_int(x));
-  return (l + q < kWave) ? __int_as_float(v) : kNegInf;
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(((l + q) & 63) << 2, __float_as_int(x)));
 }
 
 // out[c] = a[c] + b at sample t + K, for t = C*l + c.
+// Samples t + K >= 64*C lie beyond the lanes and read 0 or a wrapped value; the
+// sums they feed are still -inf: every series has at least one padding sample
+// (64*C > n_t), so a window a[c] that ends at or beyond 64*C already covers a
+// -inf sample, and wrapped values are finite or -inf, never +inf or NaN.
 template <int K, int C>
 __device__ __forceinline__ void shift_add(float (&out)[C], const float (&a)[C], const float (&b)[C]) {
   const int l = lane_id();
@@ -70,17 +73,6 @@ __device__ __forceinline__ void copy_arr(float (&out)[C], const float (&a)[C]) {
   for (int c = 0; c < C; ++c) out[c] = a[c];
 }
 
-__device__ __forceinline__ float wave_max_f(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ __forceinline__ int wave_min_i(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o));
-  return v;
-}
-
 struct Best {
   float s;
   int d, w, t;
@@ -92,22 +84,27 @@ __device__ __forceinline__ bool better(float s, int d, int w, const Best& b) {
   return d < b.d || (d == b.d && w < b.w);
 }
 
-// Max over all samples of a boxcar array and the first sample reaching it.
+// Max over all samples of a boxcar array and the first sample reaching it:
+// lane maxima by a max3 tree, the wave maximum by DPP, then one ballot per
+// register of where the maximum sits; the first sample is resolved in scalar
+// code (smallest lane, then smallest register).
 template <int C>
 __device__ __forceinline__ void max_first(const float (&b)[C], float& M, int& T) {
-  const int l = lane_id();
-  float m = kNegInf;
-  int idx = -1;
+  float m = b[0];
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const bool gt = b[c] > m;
-    m = gt ? b[c] : m;
-    idx = gt ? c : idx;
-  }
+  for (int c = 1; c + 1 < C; c += 2) m = fmaxf(m, fmaxf(b[c], b[c + 1]));
+  if ((C & 1) == 0) m = fmaxf(m, b[C - 1]);
   M = wave_max_f(m);
-  const int cand = (idx >= 0 && m == M) ? C * l + idx : 0x7fffffff;
-  T = wave_min_i(cand);
-  if (!(M > kNegInf)) T = -1;
+  if (!(M > kNegInf)) { T = -1; return; }
+  const uint64_t lanes = ballot(m == M);
+  const int L = __ffsll((long long)lanes) - 1;
+  int cbest = C;
+#pragma unroll
+  for (int c = C - 1; c >= 0; --c) {
+    const uint64_t mc = ballot(b[c] == M);
+    if ((mc >> L) & 1ull) cbest = c;
+  }
+  T = C * L + cbest;
 }
 
 // Where one cube's results go.

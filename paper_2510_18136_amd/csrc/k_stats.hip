@@ -7,25 +7,40 @@
 // and normalisation by the noise; section 3.2: a robust estimate is needed
 // because wide pulses bias a plain one).
 //
-// Launch: one workgroup of 8 waves per (tile of 16 pixels, sub-band). The
-// raw cube [t][s][p] is read in coalesced 16-pixel rows and transposed through
-// LDS so that each wave holds two pixels' series in registers (lane l, register
+// Launch: one workgroup of W waves per (tile of W pixels, sub-band), W = 16
+// (8 for series longer than 1024 samples). The
+// raw cube [t][s][p] is read in coalesced W-pixel rows and transposed through
+// LDS so that each wave holds one pixel's series in registers (lane l, register
 // j <-> sample t = 64 j + l). The z series is written time-contiguous to the
 // search layout [p][s][t].
 //
-// Exact selection: order statistics are found by adaptive histogramming of the
-// FP64 values over [lo, hi] into 256 equal bins (bin = floor((v - lo) * scale),
-// a monotone map, so rank bookkeeping is exact whatever the rounding), keeping
-// only the bin that holds the wanted rank, until <= 64 candidates remain; those
-// are sorted across the wave. Each round shrinks the range strictly, so the
-// loop ends; a degenerate range falls back to stepping through distinct values.
+// Exact selection: an order statistic of FP32 keys is found by adaptive
+// histogramming over [lo, hi] into 256 equal bins (bin = floor((v - lo) *
+// scale), a monotone map, so rank bookkeeping is exact whatever the rounding),
+// keeping only the bin that holds the wanted rank, until <= 64 candidates
+// remain; those are sorted across the wave. Each round shrinks the range
+// strictly, so the loop ends; a range too narrow to bin falls back to stepping
+// through distinct values.
+//
+// The median selects over the FP32 samples themselves. The MAD selects over
+// the FP32 roundings of the FP64 distances |x - median|: rounding is monotone,
+// so the k-th smallest FP64 distance is among the samples whose rounded
+// distance equals the k-th smallest rounded distance, and its rank among them
+// is known; those few candidates are compared in FP64.
+//
+// Normalisation divides in FP64 by Markstein's method: with r = RN(1/sigma)
+// (a correctly rounded division, once per series), q0 = RN(a*r),
+// e = fma(-q0, sigma, a) (exact) and q = fma(e, r, q0) is the correctly rounded
+// quotient a/sigma (Markstein, IBM J. Res. Dev. 34(1), 1990); sigma far from
+// 1 in exponent takes the plain division instead.
 #include "device_common.h"
 #include "nsfrb_internal.h"
 
 namespace nsfrb {
 
-constexpr int kStatTilePix = 16;
-constexpr int kStatWaves = 8;
+// Waves per workgroup (= pixels per tile): 16 for short series; 8 for long ones,
+// which need more than 128 VGPRs per wave.
+template <int V> struct StatShape { static constexpr int kWaves = V >= 32 ? 8 : 16; };
 constexpr double kMadToSigma = 1.482602218505602;
 
 struct SeriesCtx {
@@ -34,48 +49,54 @@ struct SeriesCtx {
   int n_t;
 };
 
-// k-th smallest (0-based) of the values val(j) over valid registers j.
-template <int V, class Val>
-__device__ __forceinline__ double select_kth(const Val& val, int k, const SeriesCtx& cx) {
+// Result of a selection over FP32 keys: the key value, and the rank of the
+// wanted element among the samples whose key equals it.
+struct Sel {
+  float key;
+  int rank_in_ties;
+};
+
+// k-th smallest (0-based) of the FP32 keys key[j]. Registers past the end of
+// the series hold NaN, which fails every comparison and is ignored by
+// fminf/fmaxf, so they never take part.
+template <int V>
+__device__ __forceinline__ Sel select_kth_f32(const float (&key)[V], int k, const SeriesCtx& cx) {
   const int l = lane_id();
-  double lo = __builtin_inf(), hi = -__builtin_inf();
+  float lo = __builtin_inff(), hi = -__builtin_inff();
 #pragma unroll
-  for (int j = 0; j < V; ++j) {
-    if (64 * j + l < cx.n_t) { double v = val(j); lo = fmin(lo, v); hi = fmax(hi, v); }
-  }
-  lo = wave_min(lo);
-  hi = wave_max(hi);
-  int krem = k;
-  for (int iter = 0; iter < 80; ++iter) {
-    if (!(lo < hi)) return lo;
-    const double scale = 256.0 / (hi - lo);
-    if (!(scale < 1e300)) break;   // range too narrow to bin: step through values
+  for (int j = 0; j < V; ++j)
+    { lo = fminf(lo, key[j]); hi = fmaxf(hi, key[j]); }
+  lo = wave_min_f(lo);
+  hi = wave_max_f(hi);
+  int krem = k;                                    // rank among keys in [lo, hi]
+  for (int iter = 0; iter < 48; ++iter) {
+    if (!(lo < hi)) return Sel{lo, krem};
+    const float scale = 256.0f / (hi - lo);
+    if (!(scale > 0.0f && scale < 1e30f)) break;
     cx.hist[4 * l + 0] = 0; cx.hist[4 * l + 1] = 0; cx.hist[4 * l + 2] = 0; cx.hist[4 * l + 3] = 0;
     wave_lds_sync();
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-      if (64 * j + l < cx.n_t) {
-        double v = val(j);
-        if (v >= lo && v <= hi) {
-          int b = (int)((v - lo) * scale);
-          b = b > 255 ? 255 : b;
-          atomicAdd(&cx.hist[b], 1u);
-        }
+      const float v = key[j];
+      if (v >= lo && v <= hi) {
+        int b = (int)((v - lo) * scale);
+        b = b > 255 ? 255 : b;
+        atomicAdd(&cx.hist[b], 1u);
       }
     }
     wave_lds_sync();
-    uint32_t h0 = cx.hist[4 * l], h1 = cx.hist[4 * l + 1], h2 = cx.hist[4 * l + 2], h3 = cx.hist[4 * l + 3];
-    uint32_t s = h0 + h1 + h2 + h3;
-    uint32_t incl = wave_incl_scan(s);
-    uint32_t excl = incl - s;
-    bool hit = (excl <= (uint32_t)krem) && ((uint32_t)krem < incl);
-    uint64_t m = ballot(hit);
-    int L = __ffsll((long long)m) - 1;
-    // the bin inside lane L that holds rank krem
-    uint32_t e = __shfl(excl, L);
-    uint32_t a0 = __shfl(h0, L), a1 = __shfl(h1, L), a2 = __shfl(h2, L), a3 = __shfl(h3, L);
-    uint32_t r = (uint32_t)krem - e;
-    int bsel; uint32_t before, cnt;
+    const uint32_t h0 = cx.hist[4 * l], h1 = cx.hist[4 * l + 1], h2 = cx.hist[4 * l + 2], h3 = cx.hist[4 * l + 3];
+    const uint32_t s4 = h0 + h1 + h2 + h3;
+    const uint32_t incl = wave_incl_scan(s4);
+    const uint32_t excl = incl - s4;
+    const uint64_t m = ballot((excl <= (uint32_t)krem) && ((uint32_t)krem < incl));
+    const int L = __ffsll((long long)m) - 1;
+    const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)excl, L);
+    const uint32_t a0 = (uint32_t)__builtin_amdgcn_readlane((int)h0, L), a1 = (uint32_t)__builtin_amdgcn_readlane((int)h1, L);
+    const uint32_t a2 = (uint32_t)__builtin_amdgcn_readlane((int)h2, L), a3 = (uint32_t)__builtin_amdgcn_readlane((int)h3, L);
+    const uint32_t r = (uint32_t)krem - e;
+    int bsel;
+    uint32_t before, cnt;
     if (r < a0) { bsel = 0; before = 0; cnt = a0; }
     else if (r < a0 + a1) { bsel = 1; before = a0; cnt = a1; }
     else if (r < a0 + a1 + a2) { bsel = 2; before = a0 + a1; cnt = a2; }
@@ -86,89 +107,158 @@ __device__ __forceinline__ double select_kth(const Val& val, int k, const Series
       int base = 0;
 #pragma unroll
       for (int j = 0; j < V; ++j) {
+        const float v = key[j];
         bool mem = false;
-        double v = 0.0;
-        if (64 * j + l < cx.n_t) {
-          v = val(j);
-          if (v >= lo && v <= hi) {
-            int b = (int)((v - lo) * scale);
-            b = b > 255 ? 255 : b;
-            mem = (b == B);
-          }
+        if (v >= lo && v <= hi) {
+          int b = (int)((v - lo) * scale);
+          b = b > 255 ? 255 : b;
+          mem = (b == B);
         }
-        uint64_t mm = ballot(mem);
-        if (mem) cx.list[base + lanes_below(mm)] = v;
+        const uint64_t mm = ballot(mem);
+        if (mem) cx.list[base + lanes_below(mm)] = (double)v;
         base += popc64(mm);
       }
       wave_lds_sync();
       double c = (l < (int)cnt) ? cx.list[l] : __builtin_inf();
       wave_lds_sync();
       c = wave_sort_asc(c);
-      return __shfl(c, krem);
+      const float kv = (float)readlane_d(c, krem);
+      // rank among equal keys: krem minus the candidates below it
+      const int below = popc64(ballot(l < (int)cnt && c < (double)kv));
+      return Sel{kv, krem - below};
     }
-    double nlo = __builtin_inf(), nhi = -__builtin_inf();
+    float nlo = __builtin_inff(), nhi = -__builtin_inff();
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-      if (64 * j + l < cx.n_t) {
-        double v = val(j);
-        if (v >= lo && v <= hi) {
-          int b = (int)((v - lo) * scale);
-          b = b > 255 ? 255 : b;
-          if (b == B) { nlo = fmin(nlo, v); nhi = fmax(nhi, v); }
-        }
+      const float v = key[j];
+      if (v >= lo && v <= hi) {
+        int b = (int)((v - lo) * scale);
+        b = b > 255 ? 255 : b;
+        if (b == B) { nlo = fminf(nlo, v); nhi = fmaxf(nhi, v); }
       }
     }
-    lo = wave_min(nlo);
-    hi = wave_max(nhi);
+    lo = wave_min_f(nlo);
+    hi = wave_max_f(nhi);
   }
-  // Fallback: walk the distinct values upward from lo.
-  double cur = lo;
+  // Fallback: walk the distinct keys upward from lo.
+  float cur = lo;
   for (;;) {
     int ceq = 0;
-    double nxt = __builtin_inf();
+    float nxt = __builtin_inff();
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-      if (64 * j + l < cx.n_t) {
-        double v = val(j);
-        ceq += (v == cur);
-        if (v > cur) nxt = fmin(nxt, v);
-      }
+      const float v = key[j];
+      ceq += (v == cur);
+      if (v > cur) nxt = fminf(nxt, v);
     }
     ceq = wave_sum(ceq);
-    if (krem < ceq) return cur;
+    if (krem < ceq) return Sel{cur, krem};
     krem -= ceq;
-    cur = wave_min(nxt);
-    if (!(cur < __builtin_inf())) return cur;
+    cur = wave_min_f(nxt);
+    if (!(cur < __builtin_inff())) return Sel{cur, 0};
   }
 }
 
-// The order statistic right after `a` (= the k-th smallest): the (k+1)-th.
+// The (rank)-th and (rank+1)-th smallest FP64 values val(j) among the samples
+// whose key equals kv; `second` is +inf when there is no (rank+1)-th tie.
 template <int V, class Val>
-__device__ __forceinline__ double next_order_stat(const Val& val, double a, int k, const SeriesCtx& cx) {
+__device__ __forceinline__ void resolve_ties(const float (&key)[V], float kv, int rank, const Val& val,
+                                             const SeriesCtx& cx, double& first, double& second) {
   const int l = lane_id();
-  int cle = 0;
-  double gt = __builtin_inf();
+  int base = 0;
 #pragma unroll
   for (int j = 0; j < V; ++j) {
-    if (64 * j + l < cx.n_t) {
-      double v = val(j);
-      cle += (v <= a);
-      if (v > a) gt = fmin(gt, v);
+    const bool mem = key[j] == kv;
+    const uint64_t mm = ballot(mem);
+    if (mem) {
+      const int pos = base + lanes_below(mm);
+      if (pos < 64) cx.list[pos] = val(j);
+    }
+    base += popc64(mm);
+  }
+  if (base <= 64) {
+    wave_lds_sync();
+    double c = (l < base) ? cx.list[l] : __builtin_inf();
+    wave_lds_sync();
+    c = wave_sort_asc(c);
+    first = readlane_d(c, rank);
+    second = (rank + 1 < base) ? readlane_d(c, rank + 1) : __builtin_inf();
+    return;
+  }
+  // more than 64 equal keys: step through their distinct FP64 values
+  double cur = -__builtin_inf();
+  bool have_first = false;
+  for (;;) {
+    double nxt = __builtin_inf();
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+      if (key[j] == kv) {
+        const double v = val(j);
+        if (v > cur) nxt = fmin(nxt, v);
+      }
+    cur = wave_min(nxt);
+    if (!(cur < __builtin_inf())) { second = __builtin_inf(); return; }
+    int ceq = 0;
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+      if (key[j] == kv) ceq += (val(j) == cur);
+    ceq = wave_sum(ceq);
+    if (have_first) { second = cur; return; }
+    if (rank < ceq) {
+      first = cur;
+      if (rank + 1 < ceq) { second = cur; return; }
+      have_first = true;
+    } else {
+      rank -= ceq;
     }
   }
-  cle = wave_sum(cle);
-  gt = wave_min(gt);
-  return (cle > k + 1) ? a : gt;
 }
 
-template <int V, class Val>
-__device__ __forceinline__ double median_of(const Val& val, const SeriesCtx& cx) {
+// Smallest key strictly above kv (+inf if none).
+template <int V>
+__device__ __forceinline__ float next_key(const float (&key)[V], float kv, int n_t) {
+  const int l = lane_id();
+  float m = __builtin_inff();
+#pragma unroll
+  for (int j = 0; j < V; ++j)
+    if (key[j] > kv) m = fminf(m, key[j]);
+  return wave_min_f(m);
+}
+
+// FP64 median of val(j) given FP32 keys with key[j] = RN32(val(j)) (rounding
+// is monotone); when kExact, the keys are the values themselves.
+template <bool kExact, int V, class Val>
+__device__ __forceinline__ double median_via_keys(const float (&key)[V], const Val& val, const SeriesCtx& cx) {
   const int n = cx.n_t;
   const int k1 = (n - 1) / 2;
-  double a = select_kth<V>(val, k1, cx);
-  if (n & 1) return a;
-  double b = next_order_stat<V>(val, a, k1, cx);
+  const Sel s = select_kth_f32<V>(key, k1, cx);
+  double a, b;
+  if (kExact) {
+    a = (double)s.key;
+    if (n & 1) return a;
+    // the next order statistic: a again if another sample shares the key, else the next key
+    const int l = lane_id();
+    int ceq = 0;
+#pragma unroll
+    for (int j = 0; j < V; ++j) ceq += key[j] == s.key;
+    ceq = wave_sum(ceq);
+    b = (s.rank_in_ties + 1 < ceq) ? a : (double)next_key<V>(key, s.key, n);
+  } else {
+    resolve_ties<V>(key, s.key, s.rank_in_ties, val, cx, a, b);
+    if (n & 1) return a;
+    if (!(b < __builtin_inf())) {
+      const float k2 = next_key<V>(key, s.key, n);
+      double dummy;
+      resolve_ties<V>(key, k2, 0, val, cx, b, dummy);
+    }
+  }
   return (a + b) * 0.5;
+}
+
+__device__ __forceinline__ double div_markstein(double a, double b, double r) {
+  const double q0 = a * r;
+  const double e = __builtin_fma(-q0, b, a);
+  return __builtin_fma(e, r, q0);
 }
 
 // Statistics + normalisation of one series held as xv[j] <-> t = 64 j + lane.
@@ -193,10 +283,17 @@ __device__ __forceinline__ void process_series(const float (&xv)[V], int p, int 
       med = __builtin_nan(""); sig = __builtin_nan(""); usable = false;
     } else {
       auto vx = [&](int j) { return (double)xv[j]; };
-      med = median_of<V>(vx, cx);
-      const double mm = med;
-      auto vd = [&](int j) { return fabs((double)xv[j] - mm); };
-      const double mad = median_of<V>(vd, cx);
+      med = median_via_keys<true, V>(xv, vx, cx);
+      // separate copies of the median for each use, so the compiler recomputes the
+      // FP64 differences instead of keeping all of them live
+      double mk = med, mv = med;
+      asm volatile("" : "+v"(mk));
+      asm volatile("" : "+v"(mv));
+      float dk[V];
+#pragma unroll
+      for (int j = 0; j < V; ++j) dk[j] = (float)fabs((double)xv[j] - mk);
+      auto vd = [&](int j) { return fabs((double)xv[j] - mv); };
+      const double mad = median_via_keys<false, V>(dk, vd, cx);
       sig = kMadToSigma * mad;
       usable = (sig > 0.0) && (sig < __builtin_inf());
     }
@@ -211,6 +308,9 @@ __device__ __forceinline__ void process_series(const float (&xv)[V], int p, int 
     usable = __builtin_isfinite(med) && __builtin_isfinite(sig) && sig > 0.0;
     if (!usable) nflag = 1;
   }
+  const double r = 1.0 / sig;
+  const bool fast_div = sig > 0x1p-900 && sig < 0x1p900;
+  asm volatile("" : "+v"(med));
   ST* zrow = z + ((size_t)p * n_sub + s) * n_t;
   int nbad_samples = 0;
 #pragma unroll
@@ -228,21 +328,25 @@ __device__ __forceinline__ void process_series(const float (&xv)[V], int p, int 
         zf = 0.0f;
         nbad_samples += 1;
       } else {
-        zf = (float)(((double)xv[j] - med) / sig);
+        const double a = (double)xv[j] - med;
+        zf = (float)(fast_div ? div_markstein(a, sig, r) : a / sig);
       }
       zrow[t] = from_f32<ST>(zf);
     }
+    if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bound the live FP64 temporaries
   }
   if (mode == NORM_NONE || mode == NORM_EXTERNAL) nflag += wave_sum(nbad_samples);
   if (l == 0 && nflag) atomicAdd(flag_count, (unsigned long long)nflag);
 }
 
 template <int V, typename InT, typename ST>
-__global__ __launch_bounds__(kStatWaves * kWave) void k_stats_norm(
+__global__ __launch_bounds__(StatShape<V>::kWaves * kWave) void k_stats_norm(
     const InT* __restrict__ x, int n_t, int n_sub, int n_pix, int mode,
     const double* __restrict__ med_in, const double* __restrict__ sig_in,
     double* __restrict__ med_out, double* __restrict__ sig_out,
     ST* __restrict__ z, unsigned long long* __restrict__ flag_count) {
+  constexpr int kStatWaves = StatShape<V>::kWaves;
+  constexpr int kStatTilePix = kStatWaves;        // one pixel per wave
   constexpr int VC = V < 4 ? V : 4;               // registers filled per LDS chunk
   constexpr int CT = 64 * VC;                     // samples per chunk
   constexpr int RS = kStatTilePix + 1;            // padded LDS row
@@ -256,40 +360,35 @@ __global__ __launch_bounds__(kStatWaves * kWave) void k_stats_norm(
   const int l = lane_id();
   const size_t plane = (size_t)n_sub * n_pix;
 
-  // this wave's two pixels: p0 + w and p0 + w + kStatWaves
-  float xa[V], xb[V];
+  // this wave's pixel: p0 + w
+  float xa[V];
   // ---- load: coalesced rows of 16 pixels, transposed through LDS
 #pragma unroll
   for (int ch = 0; ch < V / VC; ++ch) {
     const int t0 = ch * CT;
     for (int i = threadIdx.x; i < CT * kStatTilePix; i += kStatWaves * kWave) {
-      const int r = i / kStatTilePix, c = i % kStatTilePix;
-      const int t = t0 + r, pp = p0 + c;
+      const int rr = i / kStatTilePix, c = i % kStatTilePix;
+      const int t = t0 + rr, pp = p0 + c;
       float v = __builtin_nanf("");
       if (t < n_t && pp < n_pix) v = to_f32(x[(size_t)t * plane + (size_t)s * n_pix + pp]);
-      tile[r * RS + c] = v;
+      tile[rr * RS + c] = v;
     }
     __syncthreads();
 #pragma unroll
-    for (int jj = 0; jj < VC; ++jj) {
-      xa[ch * VC + jj] = tile[(64 * jj + l) * RS + w];
-      xb[ch * VC + jj] = tile[(64 * jj + l) * RS + w + kStatWaves];
-    }
+    for (int jj = 0; jj < VC; ++jj) xa[ch * VC + jj] = tile[(64 * jj + l) * RS + w];
     __syncthreads();
   }
   SeriesCtx cx{hist_all[w], list_all[w], n_t};
   if (p0 + w < n_pix)
     process_series<V, ST>(xa, p0 + w, s, n_t, n_sub, mode, med_in, sig_in, med_out, sig_out, z, flag_count, cx);
-  if (p0 + w + kStatWaves < n_pix)
-    process_series<V, ST>(xb, p0 + w + kStatWaves, s, n_t, n_sub, mode, med_in, sig_in, med_out, sig_out, z,
-                          flag_count, cx);
 }
 
 // ------------------------------------------------------------ launcher
 template <int V, typename InT, typename ST>
 static hipError_t launch_stats_v(const StatsLaunch& a, hipStream_t st) {
-  dim3 grid((a.n_pix + kStatTilePix - 1) / kStatTilePix, a.n_sub);
-  hipLaunchKernelGGL((k_stats_norm<V, InT, ST>), grid, dim3(kStatWaves * kWave), 0, st,
+  constexpr int W = StatShape<V>::kWaves;
+  dim3 grid((a.n_pix + W - 1) / W, a.n_sub);
+  hipLaunchKernelGGL((k_stats_norm<V, InT, ST>), grid, dim3(W * kWave), 0, st,
                      (const InT*)a.x, a.n_t, a.n_sub, a.n_pix, a.mode, a.med_in, a.sig_in,
                      a.med_out, a.sig_out, (ST*)a.z, a.flag_count);
   return hipGetLastError();

@@ -140,9 +140,9 @@ struct KernelClass {
 };
 std::string single_kernel_name(const KernelClass& k);
 // Samples per lane: odd, so 64 lanes reading rows at a common delay hit
-// distinct LDS banks; 64*C >= n_time.
+// distinct LDS banks; 64*C > n_time, so every series ends in padding.
 static int samples_per_lane(int n_time) {
-  int c = (n_time + 63) / 64;
+  int c = (n_time + 64) / 64;
   if ((c & 1) == 0) c += 1;
   return c;
 }
@@ -267,7 +267,7 @@ struct CompiledModule {
 static std::mutex g_rtc_mu;
 static std::map<std::pair<int, std::string>, CompiledModule> g_rtc_cache;
 
-static const char* kRtcOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
+static const char* kRtcOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-fno-honor-nans", "-mno-amdgpu-ieee",
                                  "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
 
 static nsfrb_status rtc_compile(const std::string& src, std::vector<char>& code) {
