@@ -85,26 +85,30 @@ __device__ __forceinline__ bool better(float s, int d, int w, const Best& b) {
 }
 
 // Max over all samples of a boxcar array and the first sample reaching it:
-// lane maxima by a max3 tree, the wave maximum by DPP, then one ballot per
-// register of where the maximum sits; the first sample is resolved in scalar
-// code (smallest lane, then smallest register).
+// lane maxima by a max3 tree, the wave maximum by DPP, the first lane holding
+// it by a ballot, and the first register of that lane holding it from a
+// per-lane index (two VALU ops per register) read from that lane.
 template <int C>
 __device__ __forceinline__ void max_first(const float (&b)[C], float& M, int& T) {
-  float m = b[0];
+  constexpr int G = (C + 2) / 3;
+  float g[G];
 #pragma unroll
-  for (int c = 1; c + 1 < C; c += 2) m = fmaxf(m, fmaxf(b[c], b[c + 1]));
-  if ((C & 1) == 0) m = fmaxf(m, b[C - 1]);
+  for (int k = 0; k < G; ++k) {
+    float v = b[3 * k];
+    if (3 * k + 1 < C) v = fmaxf(v, b[3 * k + 1]);
+    if (3 * k + 2 < C) v = fmaxf(v, b[3 * k + 2]);
+    g[k] = v;
+  }
+  float m = g[0];
+#pragma unroll
+  for (int k = 1; k < G; k += 2) m = (k + 1 < G) ? fmaxf(m, fmaxf(g[k], g[k + 1])) : fmaxf(m, g[k]);
   M = wave_max_f(m);
   if (!(M > kNegInf)) { T = -1; return; }
-  const uint64_t lanes = ballot(m == M);
-  const int L = __ffsll((long long)lanes) - 1;
-  int cbest = C;
+  const int L = __ffsll((long long)ballot(m == M)) - 1;
+  int cidx = C;
 #pragma unroll
-  for (int c = C - 1; c >= 0; --c) {
-    const uint64_t mc = ballot(b[c] == M);
-    if ((mc >> L) & 1ull) cbest = c;
-  }
-  T = C * L + cbest;
+  for (int c = C - 1; c >= 0; --c) cidx = (b[c] == M) ? c : cidx;
+  T = C * L + __builtin_amdgcn_readlane(cidx, L);
 }
 
 // Where one cube's results go.
@@ -115,18 +119,28 @@ struct CubeOut {
   int n_pix;
 };
 
+// Per-DM results are kept in lane iw of two registers and stored together
+// (lanes 0..NSFRB_NW-1 write [d][iw][p]) by flush().
 struct Reporter {
   CubeOut o;
   int p, d;
   Best best;
+  float snr_lane;
+  int toa_lane;
   __device__ __forceinline__ void emit(int iw, float M, int T) {
     const float s = (M > kNegInf) ? M / o.norms[iw] : kNegInf;
-    if (lane_id() == 0) {
-      const size_t idx = ((size_t)d * NSFRB_NW + iw) * o.n_pix + p;
-      o.snr_max[idx] = s;
-      o.toa[idx] = T;
-    }
+    const bool mine = lane_id() == iw;
+    snr_lane = mine ? s : snr_lane;
+    toa_lane = mine ? T : toa_lane;
     if (better(s, d, iw, best)) best = Best{s, d, iw, T};
+  }
+  __device__ __forceinline__ void flush() {
+    const int l = lane_id();
+    if (l < NSFRB_NW) {
+      const size_t idx = ((size_t)d * NSFRB_NW + l) * o.n_pix + p;
+      o.snr_max[idx] = snr_lane;
+      o.toa[idx] = toa_lane;
+    }
   }
   template <int C>
   __device__ __forceinline__ void operator()(int iw, const float (&b)[C]) {
@@ -191,13 +205,14 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
   }
   __syncthreads();
   const int p = p0 + slot;
-  Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, p, 0, Best{kNegInf, -1, -1, -1}};
+  Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, p, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0};
   if (p < cd.n_pix) {
     const ST* zbase = zl + (size_t)slot * n_sub * rs;
     for (int d = wq; d < cd.n_dm; d += WPP) {
       rep.d = d;
       if (cd.dmax[d] >= n_t) {
         for (int iw = 0; iw < NSFRB_NW; ++iw) rep.invalid(iw);
+        rep.flush();
         continue;
       }
       for (int pass = 0; pass < NSFRB_NPASS; ++pass) {
@@ -212,6 +227,7 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
         }
         nsfrb_chain<C>(pass, cur, rep);
       }
+      rep.flush();
     }
   }
   if (l == 0) red[wv] = rep.best;
