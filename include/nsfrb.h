@@ -206,9 +206,73 @@ nsfrb_status nsfrb_generate_noise(void* d_out, int32_t dtype, int32_t layout, in
 nsfrb_status nsfrb_inject_boxcar(void* d_cube, int32_t dtype, int32_t layout, int32_t n_pix, int32_t n_sub,
                                  int32_t n_time, int32_t pixel, int32_t t0, int32_t width, float amp,
                                  const int32_t* host_offsets, void* stream);
+/* Interference over all pixels (synthetic RFI): kind 0 adds `amp` to sample
+ * t0 of every sub-band (a zero-DM spike); kind 1 adds `amp` to samples
+ * t0 .. t0+len-1 of sub-band `sub_band` (a stripe). Samples outside are skipped. */
+nsfrb_status nsfrb_inject_rfi(void* d_cube, int32_t dtype, int32_t layout, int32_t n_pix, int32_t n_sub,
+                              int32_t n_time, int32_t kind, int32_t t0, int32_t len, int32_t sub_band, float amp,
+                              void* stream);
 /* Raw Philox4x32-10 words: block i (4 words) of counter (i, 0, 0, 0), key
  * (seed low, seed high); d_out[4 * n_blocks] uint32. */
 nsfrb_status nsfrb_philox_fill(uint32_t* d_out, int64_t n_blocks, uint64_t seed, void* stream);
+
+/* ------------------------------------------------------------- classifier
+ * Candidate classifier (paper section 2.3: a CNN over the image cube centred
+ * on the TOA -- position, time, frequency -- with convolution blocks and
+ * nonlinearities, a small fully connected head and one logit whose sigmoid is
+ * the RFI probability, trained with Adam on binary cross-entropy; sections
+ * 3.2-3.3: a probability threshold gates the S/N candidates).
+ * Network: input x[n][t][y][x][16] BF16 (sub-bands as channels, x = 32),
+ * four 3x3x3 'same' convolutions to 32 channels with ReLU, global average
+ * pool, 32->32 ReLU, 32->1 logit. Convolutions run on BF16 MFMA with FP32
+ * accumulation; master weights, Adam moments and the head are FP32.
+ * Parameters form one FP32 vector (nsfrb_classifier_param_count() values):
+ *   W_l[32][27][cin_l], b_l[32] for l = 1..4 (cin = 16, 32, 32, 32; tap index
+ *   kt*9 + ky*3 + kx), then W1[32][32], c1[32], w2[32], c2[1]. */
+typedef struct {
+  uint32_t struct_size;    /* = sizeof(nsfrb_classifier_config)                    */
+  int32_t max_batch;       /* cutouts per call, 1..1024                            */
+  int32_t n_time;          /* cutout samples (64 for the workload), 1..256         */
+  int32_t ny;              /* cutout rows (32; x is fixed at 32), 1..256           */
+  float lr, beta1, beta2, eps;   /* Adam                                            */
+  uint64_t seed;           /* weight initialisation (He-uniform convolutions)      */
+  int32_t device;
+} nsfrb_classifier_config;
+
+/* A dedispersion-aligned cutout request: the cube starts at element `offset`
+ * of the base pointer; centre pixel (px, py); DM trial index; toa. */
+typedef struct {
+  int64_t offset;
+  int32_t px, py, dm_index, toa;
+} nsfrb_cutout;
+
+typedef struct nsfrb_classifier nsfrb_classifier;
+
+int32_t nsfrb_classifier_param_count(void);
+nsfrb_status nsfrb_classifier_create(const nsfrb_classifier_config* cfg, nsfrb_classifier** out);
+nsfrb_status nsfrb_classifier_destroy(nsfrb_classifier* c);
+nsfrb_status nsfrb_classifier_params_get(nsfrb_classifier* c, float* host_out);
+nsfrb_status nsfrb_classifier_params_set(nsfrb_classifier* c, const float* host_in);
+/* Gradient of the mean loss from the last train step (same layout as the parameters). */
+nsfrb_status nsfrb_classifier_grads_get(nsfrb_classifier* c, float* host_out);
+/* One step on n cutouts (device BF16 [n][n_time][ny][32][16]) with device FP32
+ * labels (1 = RFI/noise, 0 = astrophysical): forward, BCE loss, backward and,
+ * if `update`, one Adam step. *host_loss (may be NULL) receives the mean loss
+ * (the call then waits for the stream). */
+nsfrb_status nsfrb_classifier_train_step(nsfrb_classifier* c, const void* d_cutouts, const float* d_labels, int32_t n,
+                                         int32_t update, float* host_loss, void* stream);
+/* p_rfi = sigmoid(logit) for n cutouts into device d_prob[n]. */
+nsfrb_status nsfrb_classifier_infer(nsfrb_classifier* c, const void* d_cutouts, int32_t n, float* d_prob,
+                                    void* stream);
+/* Cut n_cut dedispersion-aligned cutouts out of normalised cubes in the search
+ * layout [ny*nx][n_sub][n_time] (store dtype; n_sub must be 16): sample tt of
+ * sub-band s is z[pixel][s][toa - n_time_c/2 + tt + delta[dm][s]], pixels
+ * centred on (px, py), zero outside; d_out BF16 [n_cut][n_time_c][32][32][16]
+ * with n_time_c = the classifier's n_time. host_delays[n_dm * n_sub]. */
+nsfrb_status nsfrb_cutouts_extract(nsfrb_classifier* c, const void* d_z_base, int32_t store_dtype, int32_t nx,
+                                   int32_t ny, int32_t n_sub, int32_t n_time, const int32_t* host_delays,
+                                   int32_t n_dm, const nsfrb_cutout* host_desc, int32_t n_cut, void* d_out,
+                                   void* stream);
 
 #ifdef __cplusplus
 }

@@ -77,6 +77,37 @@ __global__ void k_inject(T* __restrict__ cube, int layout, int n_pix, int n_sub,
   }
 }
 
+// Broadband or narrowband interference over all pixels: kind 0 adds `amp` to
+// sample t0 of every sub-band (a zero-DM spike); kind 1 adds `amp` to samples
+// t0 .. t0+len-1 of sub-band s0 (a stripe).
+template <typename T>
+__global__ void k_inject_rfi(T* __restrict__ cube, int layout, int n_pix, int n_sub, int n_t, int kind, int t0, int len,
+                             int s0, float amp) {
+  const int nsb = kind == 0 ? n_sub : 1;
+  const int nts = kind == 0 ? 1 : len;
+  const long long total = (long long)n_pix * nsb * nts;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int p = (int)(i % n_pix);
+    const long long r = i / n_pix;
+    const int s = kind == 0 ? (int)(r % nsb) : s0;
+    const int t = t0 + (kind == 0 ? 0 : (int)(r % nts));
+    if (t < 0 || t >= n_t || s < 0 || s >= n_sub) continue;
+    const size_t idx = layout == 0 ? ((size_t)t * n_sub + s) * n_pix + p : ((size_t)p * n_sub + s) * n_t + t;
+    cube[idx] = from_f32<T>(to_f32(cube[idx]) + amp);
+  }
+}
+
+hipError_t launch_inject_rfi(void* cube, int dtype, int layout, int n_pix, int n_sub, int n_t, int kind, int t0, int len,
+                             int s0, float amp, hipStream_t st) {
+  const long long total = (long long)n_pix * (kind == 0 ? n_sub : len);
+  const unsigned blocks = (unsigned)(total < 65536LL * 256 ? (total + 255) / 256 : 65536LL);
+  if (dtype == DT_F32) hipLaunchKernelGGL(k_inject_rfi<float>, dim3(blocks ? blocks : 1), dim3(256), 0, st, (float*)cube, layout, n_pix, n_sub, n_t, kind, t0, len, s0, amp);
+  else if (dtype == DT_F16) hipLaunchKernelGGL(k_inject_rfi<_Float16>, dim3(blocks ? blocks : 1), dim3(256), 0, st, (_Float16*)cube, layout, n_pix, n_sub, n_t, kind, t0, len, s0, amp);
+  else hipLaunchKernelGGL(k_inject_rfi<bf16_t>, dim3(blocks ? blocks : 1), dim3(256), 0, st, (bf16_t*)cube, layout, n_pix, n_sub, n_t, kind, t0, len, s0, amp);
+  return hipGetLastError();
+}
+
 hipError_t launch_philox_fill(uint32_t* out, long long n_blocks, unsigned long long seed, hipStream_t st) {
   const long long blocks = n_blocks < 65536LL * 4 ? (n_blocks + 255) / 256 : 65536LL * 4;
   hipLaunchKernelGGL(k_philox_fill, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, st, out, n_blocks,

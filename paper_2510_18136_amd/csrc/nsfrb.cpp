@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/nsfrb.h"
+#include "host_util.h"
 #include "nsfrb_internal.h"
 #include "rtc_sources.inc"   // kRtcDeviceCommon, kRtcSearchBody (generated at build time)
 
@@ -38,6 +39,11 @@ static nsfrb_status fail(nsfrb_status st, const std::string& msg) {
       return fail(e_ == hipErrorOutOfMemory ? NSFRB_ERR_OUT_OF_MEMORY : NSFRB_ERR_DEVICE,  \
                   std::string(#expr) + ": " + hipGetErrorString(e_));                      \
   } while (0)
+
+namespace nsfrb {
+nsfrb_status host_fail(nsfrb_status st, const std::string& msg) { return fail(st, msg); }
+void host_clear_error() { g_last_error.clear(); }
+}  // namespace nsfrb
 
 extern "C" const char* nsfrb_version(void) { return "nsfrb-mi355x 0.1 (gfx950)"; }
 extern "C" const char* nsfrb_last_error(void) { return g_last_error.c_str(); }

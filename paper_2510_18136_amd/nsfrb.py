@@ -30,7 +30,10 @@ EXPORTS = [
     "nsfrb_profiling_enable", "nsfrb_stage_times_get", "nsfrb_search_plan_info",
     "nsfrb_batch_create", "nsfrb_batch_destroy", "nsfrb_batch_run", "nsfrb_batch_run_separate",
     "nsfrb_batch_use_graph", "nsfrb_batch_candidates_get", "nsfrb_batch_maps_get", "nsfrb_batch_info_get",
-    "nsfrb_generate_noise", "nsfrb_inject_boxcar", "nsfrb_philox_fill",
+    "nsfrb_generate_noise", "nsfrb_inject_boxcar", "nsfrb_philox_fill", "nsfrb_inject_rfi",
+    "nsfrb_classifier_param_count", "nsfrb_classifier_create", "nsfrb_classifier_destroy",
+    "nsfrb_classifier_params_get", "nsfrb_classifier_params_set", "nsfrb_classifier_grads_get",
+    "nsfrb_classifier_train_step", "nsfrb_classifier_infer", "nsfrb_cutouts_extract",
 ]
 
 
@@ -52,6 +55,18 @@ class Config(ctypes.Structure):
 class Candidate(ctypes.Structure):
     _fields_ = [("x", ctypes.c_int32), ("y", ctypes.c_int32), ("dm_index", ctypes.c_int32),
                 ("width_index", ctypes.c_int32), ("toa", ctypes.c_int32), ("snr", ctypes.c_float)]
+
+
+class ClassifierConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_batch", ctypes.c_int32), ("n_time", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("device", ctypes.c_int32)]
+
+
+class CutoutDesc(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("px", ctypes.c_int32), ("py", ctypes.c_int32),
+                ("dm_index", ctypes.c_int32), ("toa", ctypes.c_int32)]
 
 
 class NsfrbError(RuntimeError):
@@ -106,6 +121,17 @@ def lib():
             "nsfrb_inject_boxcar": ([vp, i32, i32, i32, i32, i32, i32, i32, i32, ctypes.c_float, pi32, vp],
                                     ctypes.c_int),
             "nsfrb_philox_fill": ([vp, ctypes.c_int64, ctypes.c_uint64, vp], ctypes.c_int),
+            "nsfrb_inject_rfi": ([vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, ctypes.c_float, vp], ctypes.c_int),
+            "nsfrb_classifier_param_count": ([], ctypes.c_int32),
+            "nsfrb_classifier_create": ([ctypes.POINTER(ClassifierConfig), ctypes.POINTER(vp)], ctypes.c_int),
+            "nsfrb_classifier_destroy": ([vp], ctypes.c_int),
+            "nsfrb_classifier_params_get": ([vp, pf], ctypes.c_int),
+            "nsfrb_classifier_params_set": ([vp, pf], ctypes.c_int),
+            "nsfrb_classifier_grads_get": ([vp, pf], ctypes.c_int),
+            "nsfrb_classifier_train_step": ([vp, vp, vp, i32, i32, pf, vp], ctypes.c_int),
+            "nsfrb_classifier_infer": ([vp, vp, i32, vp, vp], ctypes.c_int),
+            "nsfrb_cutouts_extract": ([vp, vp, i32, i32, i32, i32, i32, pi32, i32, ctypes.POINTER(CutoutDesc),
+                                       i32, vp, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -369,3 +395,80 @@ def inject_boxcar(d_ptr, dtype, layout, n_pix, n_sub, n_time, pixel, t0, width, 
 def philox_fill(d_ptr, n_blocks, seed, stream=0):
     check(lib().nsfrb_philox_fill(ctypes.c_void_p(int(d_ptr)), int(n_blocks), ctypes.c_uint64(seed),
                                   ctypes.c_void_p(int(stream))))
+
+
+def inject_rfi(d_ptr, dtype, layout, n_pix, n_sub, n_time, kind, t0, length=1, sub_band=0, amp=1.0, stream=0):
+    """kind 'spike': one sample, all sub-bands; kind 'stripe': one sub-band over [t0, t0+length)."""
+    k = {"spike": 0, "stripe": 1}[kind]
+    check(lib().nsfrb_inject_rfi(ctypes.c_void_p(int(d_ptr)), DTYPES[dtype], LAYOUTS[layout], n_pix, n_sub, n_time,
+                                 k, int(t0), int(length), int(sub_band), float(amp), ctypes.c_void_p(int(stream))))
+
+
+class Classifier:
+    """The candidate classifier (3-D CNN, BF16 MFMA training and inference)."""
+
+    def __init__(self, max_batch=64, n_time=64, ny=32, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=1,
+                 device=0):
+        c = ClassifierConfig()
+        c.struct_size = ctypes.sizeof(ClassifierConfig)
+        c.max_batch, c.n_time, c.ny = int(max_batch), int(n_time), int(ny)
+        c.lr, c.beta1, c.beta2, c.eps = float(lr), float(beta1), float(beta2), float(eps)
+        c.seed, c.device = int(seed), int(device)
+        self.cfg = c
+        h = ctypes.c_void_p()
+        check(lib().nsfrb_classifier_create(ctypes.byref(c), ctypes.byref(h)))
+        self.h = h
+        self.n_params = int(lib().nsfrb_classifier_param_count())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nsfrb_classifier_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def params(self):
+        out = np.zeros(self.n_params, np.float32)
+        check(lib().nsfrb_classifier_params_get(self.h, _ptr(out, ctypes.c_float)))
+        return out
+
+    def set_params(self, theta):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        assert t.size == self.n_params
+        check(lib().nsfrb_classifier_params_set(self.h, _ptr(t, ctypes.c_float)))
+
+    def grads(self):
+        out = np.zeros(self.n_params, np.float32)
+        check(lib().nsfrb_classifier_grads_get(self.h, _ptr(out, ctypes.c_float)))
+        return out
+
+    def train_step(self, d_cutouts, d_labels, n, update=True, stream=0, want_loss=True):
+        loss = ctypes.c_float(float("nan"))
+        check(lib().nsfrb_classifier_train_step(self.h, ctypes.c_void_p(int(d_cutouts)), ctypes.c_void_p(int(d_labels)),
+                                                int(n), 1 if update else 0,
+                                                ctypes.byref(loss) if want_loss else None,
+                                                ctypes.c_void_p(int(stream))))
+        return loss.value
+
+    def infer(self, d_cutouts, n, d_prob, stream=0):
+        check(lib().nsfrb_classifier_infer(self.h, ctypes.c_void_p(int(d_cutouts)), int(n),
+                                           ctypes.c_void_p(int(d_prob)), ctypes.c_void_p(int(stream))))
+
+    def cutouts(self, d_z_base, store_dtype, nx, ny, n_sub, n_time, delays, descs, d_out, stream=0):
+        """descs: list of (offset, px, py, dm_index, toa)."""
+        dl = np.ascontiguousarray(delays, dtype=np.int32)
+        arr = (CutoutDesc * len(descs))(*[CutoutDesc(int(o), int(x), int(y), int(d), int(t))
+                                            for (o, x, y, d, t) in descs])
+        check(lib().nsfrb_cutouts_extract(self.h, ctypes.c_void_p(int(d_z_base)), DTYPES[store_dtype], int(nx),
+                                          int(ny), int(n_sub), int(n_time), _ptr(dl, ctypes.c_int32), dl.shape[0],
+                                          arr, len(descs), ctypes.c_void_p(int(d_out)), ctypes.c_void_p(int(stream))))
