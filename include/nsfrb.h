@@ -146,6 +146,10 @@ nsfrb_status nsfrb_noise_stats_set(nsfrb_search* h, const double* med, const dou
 /* Normalised cube in the search layout [ny*nx][n_sub][n_time], store dtype
  * (2 or 4 bytes per element). */
 nsfrb_status nsfrb_zcube_get(nsfrb_search* h, void* host_out);
+/* Device pointer of the normalised cube of the last run (the handle's buffer,
+ * or the input itself for LAYOUT_PST), valid until the next run or destroy.
+ * Does not wait. NOT_READY before any run. */
+nsfrb_status nsfrb_zcube_device(nsfrb_search* h, const void** d_z);
 /* Series (or, for NONE/EXTERNAL, samples) flagged as unusable by the last run. */
 nsfrb_status nsfrb_flag_count_get(nsfrb_search* h, int64_t* count);
 
@@ -189,6 +193,11 @@ nsfrb_status nsfrb_batch_use_graph(nsfrb_batch* b, int32_t on);
 nsfrb_status nsfrb_batch_candidates_get(nsfrb_batch* b, int32_t cube, nsfrb_candidate* host_out,
                                         int32_t capacity, int32_t* n_written, int32_t* n_total);
 nsfrb_status nsfrb_batch_maps_get(nsfrb_batch* b, int32_t cube, float* snr_max, int32_t* toa);
+/* Per-pixel best trial and normalised-cube pointer of one cube, as
+ * nsfrb_best_get and nsfrb_zcube_device of a single search. */
+nsfrb_status nsfrb_batch_best_get(nsfrb_batch* b, int32_t cube, float* snr, int32_t* dm_index, int32_t* width_index,
+                                  int32_t* toa);
+nsfrb_status nsfrb_batch_zcube_device(nsfrb_batch* b, int32_t cube, const void** d_z);
 /* info[0] work items, [1] persistent grid size, [2] LDS bytes, [3] kernel
  * classes, [4] 1 if the last run replayed a captured graph. */
 nsfrb_status nsfrb_batch_info_get(nsfrb_batch* b, int64_t* info);
@@ -206,6 +215,19 @@ nsfrb_status nsfrb_generate_noise(void* d_out, int32_t dtype, int32_t layout, in
 nsfrb_status nsfrb_inject_boxcar(void* d_cube, int32_t dtype, int32_t layout, int32_t n_pix, int32_t n_sub,
                                  int32_t n_time, int32_t pixel, int32_t t0, int32_t width, float amp,
                                  const int32_t* host_offsets, void* stream);
+/* Many boxcars in one launch: record i adds amp to samples
+ * t0 + host_offsets[i*n_sub + s] ... + width - 1 of every sub-band s of pixel
+ * `pixel` of cube d_cubes[cube] (a HOST array of n_cubes DEVICE pointers, all
+ * cubes of one shape, dtype and layout). Samples outside are skipped. Records
+ * must name distinct (cube, pixel) pairs (INVALID_ARG otherwise); 1 <= n <=
+ * 65535. Synchronous, like nsfrb_inject_boxcar. */
+typedef struct {
+  int32_t cube, pixel, t0, width;
+  float amp;
+} nsfrb_boxcar;
+nsfrb_status nsfrb_inject_boxcars(void* const* d_cubes, int32_t n_cubes, int32_t dtype, int32_t layout, int32_t n_pix,
+                                  int32_t n_sub, int32_t n_time, const nsfrb_boxcar* host_boxcars,
+                                  const int32_t* host_offsets, int32_t n, void* stream);
 /* Interference over all pixels (synthetic RFI): kind 0 adds `amp` to sample
  * t0 of every sub-band (a zero-DM spike); kind 1 adds `amp` to samples
  * t0 .. t0+len-1 of sub-band `sub_band` (a stripe). Samples outside are skipped. */
@@ -223,12 +245,15 @@ nsfrb_status nsfrb_philox_fill(uint32_t* d_out, int64_t n_blocks, uint64_t seed,
  * the RFI probability, trained with Adam on binary cross-entropy; sections
  * 3.2-3.3: a probability threshold gates the S/N candidates).
  * Network: input x[n][t][y][x][16] BF16 (sub-bands as channels, x = 32),
- * four 3x3x3 'same' convolutions to 32 channels with ReLU, global average
- * pool, 32->32 ReLU, 32->1 logit. Convolutions run on BF16 MFMA with FP32
- * accumulation; master weights, Adam moments and the head are FP32.
+ * four 3x3x3 'same' convolutions to 32 channels with ReLU, then 64 head
+ * features: the global maximum of every channel (the first position in
+ * (t, y, x) order on ties) and the channel values at the candidate's own
+ * position (t = n_time/2, y = ny/2, x = 16), then 64->32 ReLU, 32->1 logit.
+ * Convolutions run on BF16 MFMA with FP32 accumulation; master weights, Adam
+ * moments and the head are FP32.
  * Parameters form one FP32 vector (nsfrb_classifier_param_count() values):
  *   W_l[32][27][cin_l], b_l[32] for l = 1..4 (cin = 16, 32, 32, 32; tap index
- *   kt*9 + ky*3 + kx), then W1[32][32], c1[32], w2[32], c2[1]. */
+ *   kt*9 + ky*3 + kx), then W1[32][64], c1[32], w2[32], c2[1]. */
 typedef struct {
   uint32_t struct_size;    /* = sizeof(nsfrb_classifier_config)                    */
   int32_t max_batch;       /* cutouts per call, 1..1024                            */
@@ -239,10 +264,11 @@ typedef struct {
   int32_t device;
 } nsfrb_classifier_config;
 
-/* A dedispersion-aligned cutout request: the cube starts at element `offset`
- * of the base pointer; centre pixel (px, py); DM trial index; toa. */
+/* A dedispersion-aligned cutout request: index of its cube in the table of
+ * cube pointers; centre pixel (px, py); DM trial index; toa (a candidate's
+ * first boxcar sample at f_ref, placed at cutout sample n_time/2). */
 typedef struct {
-  int64_t offset;
+  int64_t cube;
   int32_t px, py, dm_index, toa;
 } nsfrb_cutout;
 
@@ -253,6 +279,8 @@ nsfrb_status nsfrb_classifier_create(const nsfrb_classifier_config* cfg, nsfrb_c
 nsfrb_status nsfrb_classifier_destroy(nsfrb_classifier* c);
 nsfrb_status nsfrb_classifier_params_get(nsfrb_classifier* c, float* host_out);
 nsfrb_status nsfrb_classifier_params_set(nsfrb_classifier* c, const float* host_in);
+/* Learning rate of later Adam steps (a schedule); the moments are kept. */
+nsfrb_status nsfrb_classifier_set_lr(nsfrb_classifier* c, float lr);
 /* Gradient of the mean loss from the last train step (same layout as the parameters). */
 nsfrb_status nsfrb_classifier_grads_get(nsfrb_classifier* c, float* host_out);
 /* One step on n cutouts (device BF16 [n][n_time][ny][32][16]) with device FP32
@@ -264,15 +292,22 @@ nsfrb_status nsfrb_classifier_train_step(nsfrb_classifier* c, const void* d_cuto
 /* p_rfi = sigmoid(logit) for n cutouts into device d_prob[n]. */
 nsfrb_status nsfrb_classifier_infer(nsfrb_classifier* c, const void* d_cutouts, int32_t n, float* d_prob,
                                     void* stream);
-/* Cut n_cut dedispersion-aligned cutouts out of normalised cubes in the search
- * layout [ny*nx][n_sub][n_time] (store dtype; n_sub must be 16): sample tt of
- * sub-band s is z[pixel][s][toa - n_time_c/2 + tt + delta[dm][s]], pixels
- * centred on (px, py), zero outside; d_out BF16 [n_cut][n_time_c][32][32][16]
- * with n_time_c = the classifier's n_time. host_delays[n_dm * n_sub]. */
-nsfrb_status nsfrb_cutouts_extract(nsfrb_classifier* c, const void* d_z_base, int32_t store_dtype, int32_t nx,
-                                   int32_t ny, int32_t n_sub, int32_t n_time, const int32_t* host_delays,
-                                   int32_t n_dm, const nsfrb_cutout* host_desc, int32_t n_cut, void* d_out,
-                                   void* stream);
+/* Cut n_cut dedispersion-aligned cutouts (section 2.3: the classifier sees
+ * the image cube centred on the candidate's TOA) out of normalised cubes in
+ * the search layout [ny*nx][n_sub][n_time] (store dtype; n_sub must be 16).
+ * d_z_cubes is a HOST array of n_cubes DEVICE pointers (e.g. from
+ * nsfrb_zcube_device); all cubes share the shape and the delay table
+ * host_delays[n_dm * n_sub] (delta[d][s] in samples). Sample tt of sub-band s
+ * of cutout k is z[pixel][s][toa - n_time_c/2 + tt + delta[dm][s]], pixels
+ * centred on (px, py), zero outside the image or the series; d_out BF16
+ * [n_cut][n_time_c][32][32][16], n_time_c = the classifier's n_time (its ny
+ * must be 32). Waits for `stream` (the descriptor buffers are reused), then
+ * enqueues the copy on it. INVALID_ARG for NULL pointers, n_cut outside
+ * 1..max_batch or a descriptor whose cube or DM index is out of range. */
+nsfrb_status nsfrb_cutouts_extract(nsfrb_classifier* c, const void* const* d_z_cubes, int32_t n_cubes,
+                                   int32_t store_dtype, int32_t nx, int32_t ny, int32_t n_sub, int32_t n_time,
+                                   const int32_t* host_delays, int32_t n_dm, const nsfrb_cutout* host_desc,
+                                   int32_t n_cut, void* d_out, void* stream);
 
 #ifdef __cplusplus
 }

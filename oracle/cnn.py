@@ -2,21 +2,30 @@
 
 Paper section 2.3 classifies candidates with a CNN over the image cube
 centred on the TOA (position, time, frequency): convolution blocks with
-nonlinearities, a small fully connected head, a single logit whose sigmoid is
-the RFI probability, trained with Adam on a binary cross-entropy loss. The
-network here has the fixed shape of the workload this project targets:
+nonlinearities and max-pooling, a small fully connected head, a single logit
+whose sigmoid is the RFI probability, trained with Adam on a binary
+cross-entropy loss. The network here has the fixed shape of the workload this
+project targets:
 
   input   x[n][t][y][x][s]           64 x 32 x 32 samples, 16 sub-bands as channels
   conv_l  a_l = relu(b_l + sum_{tap, ci} W_l[co][tap][ci] * a_{l-1}[pos + tap - 1][ci])
           3x3x3 taps over (t, y, x), zero padding, 32 output channels, l = 1..4
-  pool    h[n][c] = mean over (t, y, x) of a_4
-  fc1     r = relu(W1 h + c1)   (32 -> 32)
+  pool    m[n][c] = max over (t, y, x) of a_4 (ties: first position in (t, y, x) order)
+          q[n][c] = a_4 at the candidate's own position (T/2, Y/2, X/2): the cutout
+                    puts the candidate's TOA at sample T/2 and its pixel at the centre
+          h = [m, q]                 (64 features)
+  fc1     r = relu(W1 h + c1)   (64 -> 32)
   fc2     z = w2 . r + c2        (32 -> 1), p_rfi = sigmoid(z)
   loss    mean_n [max(z, 0) - z*label + log(1 + exp(-|z|))]
 
+The global max pool follows the paper's max-pooling; the candidate-position
+features are there because any global pool is blind to where in the cutout a
+feature sits, so it cannot tell a source at the centre from a bright source
+beside a faint sidelobe copy at the centre.
+
 Parameters are one flat FP32 vector in the order
   W_1[32][27][16], b_1[32], W_2[32][27][32], b_2[32], W_3, b_3, W_4, b_4,
-  W1[32][32], c1[32], w2[32], c2[1]   (97,985 values),
+  W1[32][64], c1[32], w2[32], c2[1]   (99,009 values),
 with tap index kt*9 + ky*3 + kx.
 
 `bf16=True` reproduces the rounding points of the GPU path: inputs, conv
@@ -35,7 +44,7 @@ def param_shapes():
     shapes = []
     for cin in LAYER_CIN:
         shapes += [(C_HID, N_TAP, cin), (C_HID,)]
-    shapes += [(C_HID, C_HID), (C_HID,), (C_HID,), (1,)]
+    shapes += [(C_HID, 2 * C_HID), (C_HID,), (C_HID,), (1,)]
     return shapes
 
 
@@ -107,20 +116,39 @@ def forward(theta, x, bf16_points=False):
     for l in range(4):
         W, b = P[2 * l], P[2 * l + 1]
         acts.append(rnd(np.maximum(conv3(acts[-1], rnd(W), b), 0.0)))
-    h = acts[-1].mean(axis=(1, 2, 3))
+    a4 = acts[-1]
+    n, T, Y, X, C = a4.shape
+    flat = a4.reshape(n, T * Y * X, C)
+    arg = np.argmax(flat, axis=1)                      # first maximum along (t, y, x)
+    m = np.take_along_axis(flat, arg[:, None, :], axis=1)[:, 0, :]
+    q = a4[:, T // 2, Y // 2, X // 2, :]
+    h = np.concatenate([m, q], axis=1)
     W1, c1, w2, c2 = P[8], P[9], P[10], P[11]
     u = h @ W1.T + c1
     r = np.maximum(u, 0.0)
     z = r @ w2 + c2[0]
-    return dict(acts=acts, h=h, u=u, r=r, z=z)
+    return dict(acts=acts, arg=arg, h=h, u=u, r=r, z=z)
+
+
+def pool_backward(a4_shape, arg, dh):
+    """d(loss)/d(a_4) from d(loss)/d(h): the max half goes to each channel's
+    first maximum, the other half to the candidate position."""
+    n, T, Y, X, C = a4_shape
+    d = np.zeros((n, T * Y * X, C))
+    for i in range(n):
+        d[i, arg[i], np.arange(C)] += dh[i, :C]
+    d = d.reshape(a4_shape)
+    d[:, T // 2, Y // 2, X // 2, :] += dh[:, C:]
+    return d
 
 
 def bce_logits(z, y):
     return float(np.mean(np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z)))))
 
 
-def loss_and_grad(theta, x, labels, bf16_points=False):
-    """Mean BCE-with-logits loss and its gradient w.r.t. the flat parameters."""
+def loss_and_grad(theta, x, labels, bf16_points=False, input_grad=False):
+    """Mean BCE-with-logits loss and its gradient w.r.t. the flat parameters
+    (and, with input_grad, w.r.t. the input cutouts as a fourth value)."""
     P = unpack(theta)
     rnd = bf16 if bf16_points else (lambda a: a)
     f = forward(theta, x, bf16_points)
@@ -135,16 +163,16 @@ def loss_and_grad(theta, x, labels, bf16_points=False):
     g_W1 = du.T @ f["h"]
     g_c1 = du.sum(axis=0)
     dh = du @ W1
-    a4 = f["acts"][4]
-    npos = a4.shape[1] * a4.shape[2] * a4.shape[3]
-    dpost = np.broadcast_to((dh / npos)[:, None, None, None, :], a4.shape)
+    dpost = pool_backward(f["acts"][4].shape, f["arg"], dh)
     grads = [None] * 12
     grads[8], grads[9], grads[10], grads[11] = g_W1, g_c1, g_w2, g_c2
     for l in (3, 2, 1, 0):
         dpre = rnd(dpost * (f["acts"][l + 1] > 0))
-        dW, db, dx = conv3_backward(f["acts"][l], rnd(P[2 * l]), dpre, need_dx=l > 0)
+        dW, db, dx = conv3_backward(f["acts"][l], rnd(P[2 * l]), dpre, need_dx=l > 0 or input_grad)
         grads[2 * l], grads[2 * l + 1] = dW, db
         dpost = dx
+    if input_grad:
+        return loss, pack(grads), f, dpost
     return loss, pack(grads), f
 
 
@@ -155,7 +183,7 @@ def init_params(seed):
     for cin in LAYER_CIN:
         lim = np.sqrt(6.0 / (N_TAP * cin))
         parts += [rng.uniform(-lim, lim, (C_HID, N_TAP, cin)), np.zeros(C_HID)]
-    lim = np.sqrt(6.0 / C_HID)
-    parts += [rng.uniform(-lim, lim, (C_HID, C_HID)), np.zeros(C_HID),
-              rng.uniform(-lim, lim, C_HID), np.zeros(1)]
+    lim1, lim2 = np.sqrt(6.0 / (2 * C_HID)), np.sqrt(6.0 / C_HID)
+    parts += [rng.uniform(-lim1, lim1, (C_HID, 2 * C_HID)), np.zeros(C_HID),
+              rng.uniform(-lim2, lim2, C_HID), np.zeros(1)]
     return pack(parts)

@@ -21,7 +21,7 @@ constexpr int kCin = 16, kCh = 32, kTap = 27, kX = 32;
 constexpr int kLayerCin[4] = {kCin, kCh, kCh, kCh};
 
 // Offsets of the parameter blocks in the flat FP32 vector:
-// W_l[32][27][cin], b_l[32] for l = 1..4, then W1[32][32], c1[32], w2[32], c2[1].
+// W_l[32][27][cin], b_l[32] for l = 1..4, then W1[32][64], c1[32], w2[32], c2[1].
 struct Layout {
   int w[4], b[4], head, total;
   Layout() {
@@ -33,7 +33,7 @@ struct Layout {
       o += kCh;
     }
     head = o;
-    o += kCh * kCh + kCh + kCh + 1;
+    o += kCh * 2 * kCh + kCh + kCh + 1;
     total = o;
   }
 };
@@ -63,14 +63,17 @@ struct nsfrb_classifier {
   uint16_t* d_dpre[2] = {};    // pre-activation gradients (ping-pong)
   float* d_part = nullptr;
   float* d_part_db = nullptr;
-  float* d_h = nullptr;
+  float* d_h = nullptr;         // head input [n][64]: channel maxima, candidate-position features
   float* d_dh = nullptr;
+  int* d_arg = nullptr;         // position of each channel's maximum [n][32]
   float* d_logits = nullptr;
   float* d_prob = nullptr;
   float* d_loss = nullptr;
   void* d_cut_desc = nullptr;
   int* d_delays = nullptr;
   int delays_cap = 0;
+  const void** d_cube_ptrs = nullptr;
+  int cube_ptrs_cap = 0;
   float* h_loss = nullptr;
   long long step = 0;
   bool weights_dirty = true;
@@ -81,8 +84,8 @@ namespace {
 void release(nsfrb_classifier* c) {
   if (!c) return;
   hipSetDevice(c->device);
-  void* bufs[] = {c->d_theta, c->d_m, c->d_v, c->d_grad, c->d_part, c->d_part_db, c->d_h, c->d_dh,
-                  c->d_logits, c->d_prob, c->d_loss, c->d_cut_desc, c->d_delays};
+  void* bufs[] = {c->d_theta, c->d_m, c->d_v, c->d_grad, c->d_part, c->d_part_db, c->d_h, c->d_dh, (void*)c->d_arg,
+                  c->d_logits, c->d_prob, c->d_loss, c->d_cut_desc, c->d_delays, (void*)c->d_cube_ptrs};
   for (void* b : bufs)
     if (b) hipFree(b);
   for (int l = 0; l < 4; ++l) {
@@ -108,6 +111,9 @@ nsfrb_status prep_weights(nsfrb_classifier* c, hipStream_t st) {
   return NSFRB_OK;
 }
 
+// Flat (t, y, x) index of the candidate's own position: TOA at sample T/2, pixel at the centre.
+int centre_pos(const nsfrb_classifier* c) { return ((c->cfg.n_time / 2) * c->cfg.ny + c->cfg.ny / 2) * kX + kX / 2; }
+
 nsfrb_status forward(nsfrb_classifier* c, const uint16_t* x, int n, hipStream_t st) {
   const int T = c->cfg.n_time, Y = c->cfg.ny;
   if (c->weights_dirty) {
@@ -119,7 +125,7 @@ nsfrb_status forward(nsfrb_classifier* c, const uint16_t* x, int n, hipStream_t 
     NSFRB_HIP_TRY(launch_conv_fwd(kLayerCin[l], in, c->d_wf[l], c->d_theta + kL.b[l], c->d_act[l], n, T, Y, st));
     in = c->d_act[l];
   }
-  NSFRB_HIP_TRY(launch_pool(c->d_act[3], n, T * Y * kX, c->d_h, st));
+  NSFRB_HIP_TRY(launch_pool(c->d_act[3], n, T * Y * kX, centre_pos(c), c->d_h, c->d_arg, st));
   return NSFRB_OK;
 }
 
@@ -156,22 +162,23 @@ extern "C" nsfrb_status nsfrb_classifier_create(const nsfrb_classifier_config* c
   const size_t items = (size_t)wgrad_items((int)N, cfg->n_time);
   NSFRB_HIP_TRY(dalloc(&c->d_part, items * kTap * kCh * kCh));
   NSFRB_HIP_TRY(dalloc(&c->d_part_db, items * kCh));
-  NSFRB_HIP_TRY(dalloc(&c->d_h, N * kCh));
-  NSFRB_HIP_TRY(dalloc(&c->d_dh, N * kCh));
+  NSFRB_HIP_TRY(dalloc(&c->d_h, N * 2 * kCh));
+  NSFRB_HIP_TRY(dalloc(&c->d_dh, N * 2 * kCh));
+  NSFRB_HIP_TRY(dalloc(&c->d_arg, N * kCh));
   NSFRB_HIP_TRY(dalloc(&c->d_logits, N));
   NSFRB_HIP_TRY(dalloc(&c->d_prob, N));
   NSFRB_HIP_TRY(dalloc(&c->d_loss, 4));
   NSFRB_HIP_TRY(hipHostMalloc((void**)&c->h_loss, sizeof(float) * 4, hipHostMallocDefault));
-  // He-uniform convolution weights, uniform(+-sqrt(6/32)) head weights, zero biases
+  // He-uniform convolution weights, uniform(+-sqrt(6/fan_in)) head weights, zero biases
   std::vector<float> th(P, 0.f);
   uint64_t s = cfg->seed;
   for (int l = 0; l < 4; ++l) {
     const double lim = std::sqrt(6.0 / (kTap * kLayerCin[l]));
     for (int i = 0; i < kCh * kTap * kLayerCin[l]; ++i) th[kL.w[l] + i] = (float)((2 * uniform01(s) - 1) * lim);
   }
-  const double lim = std::sqrt(6.0 / kCh);
-  for (int i = 0; i < kCh * kCh; ++i) th[kL.head + i] = (float)((2 * uniform01(s) - 1) * lim);
-  for (int i = 0; i < kCh; ++i) th[kL.head + kCh * kCh + kCh + i] = (float)((2 * uniform01(s) - 1) * lim);
+  const double lim1 = std::sqrt(6.0 / (2 * kCh)), lim2 = std::sqrt(6.0 / kCh);
+  for (int i = 0; i < kCh * 2 * kCh; ++i) th[kL.head + i] = (float)((2 * uniform01(s) - 1) * lim1);
+  for (int i = 0; i < kCh; ++i) th[kL.head + 2 * kCh * kCh + kCh + i] = (float)((2 * uniform01(s) - 1) * lim2);
   NSFRB_HIP_TRY(hipMemcpy(c->d_theta, th.data(), P * sizeof(float), hipMemcpyHostToDevice));
   NSFRB_HIP_TRY(hipMemset(c->d_m, 0, P * sizeof(float)));
   NSFRB_HIP_TRY(hipMemset(c->d_v, 0, P * sizeof(float)));
@@ -211,6 +218,14 @@ extern "C" nsfrb_status nsfrb_classifier_params_set(nsfrb_classifier* c, const f
   return NSFRB_OK;
 }
 
+extern "C" nsfrb_status nsfrb_classifier_set_lr(nsfrb_classifier* c, float lr) {
+  host_clear_error();
+  if (!c) return host_fail(NSFRB_ERR_INVALID_ARG, "classifier is NULL");
+  if (!(lr >= 0.f) || !std::isfinite(lr)) return host_fail(NSFRB_ERR_INVALID_ARG, "lr must be finite and >= 0");
+  c->cfg.lr = lr;
+  return NSFRB_OK;
+}
+
 extern "C" nsfrb_status nsfrb_classifier_grads_get(nsfrb_classifier* c, float* host) {
   host_clear_error();
   if (!c || !host) return host_fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
@@ -233,7 +248,7 @@ extern "C" nsfrb_status nsfrb_classifier_train_step(nsfrb_classifier* c, const v
   if (s != NSFRB_OK) return s;
   NSFRB_HIP_TRY(launch_head(c->d_h, d_labels, n, c->d_theta + kL.head, c->d_grad + kL.head, c->d_dh, c->d_logits,
                             c->d_prob, c->d_loss, 1, st));
-  NSFRB_HIP_TRY(launch_pool_backward(c->d_dh, c->d_act[3], n, npos, c->d_dpre[0], st));
+  NSFRB_HIP_TRY(launch_pool_backward(c->d_dh, c->d_arg, c->d_act[3], n, npos, centre_pos(c), c->d_dpre[0], st));
   int cur = 0;
   for (int l = 3; l >= 0; --l) {
     const uint16_t* in = l ? c->d_act[l - 1] : x;
@@ -275,20 +290,25 @@ extern "C" nsfrb_status nsfrb_classifier_infer(nsfrb_classifier* c, const void* 
   return NSFRB_OK;
 }
 
-extern "C" nsfrb_status nsfrb_cutouts_extract(nsfrb_classifier* c, const void* d_z_base, int32_t store_dtype, int32_t nx,
-                                              int32_t ny, int32_t n_sub, int32_t n_time, const int32_t* host_delays,
-                                              int32_t n_dm, const nsfrb_cutout* host_desc, int32_t n_cut,
-                                              void* d_out, void* stream) {
+extern "C" nsfrb_status nsfrb_cutouts_extract(nsfrb_classifier* c, const void* const* d_z_cubes, int32_t n_cubes,
+                                              int32_t store_dtype, int32_t nx, int32_t ny, int32_t n_sub,
+                                              int32_t n_time, const int32_t* host_delays, int32_t n_dm,
+                                              const nsfrb_cutout* host_desc, int32_t n_cut, void* d_out,
+                                              void* stream) {
   host_clear_error();
-  if (!c || !d_z_base || !host_delays || !host_desc || !d_out) return host_fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  if (!c || !d_z_cubes || !host_delays || !host_desc || !d_out) return host_fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  if (n_cubes < 1) return host_fail(NSFRB_ERR_INVALID_ARG, "n_cubes must be >= 1");
+  for (int i = 0; i < n_cubes; ++i)
+    if (!d_z_cubes[i]) return host_fail(NSFRB_ERR_INVALID_ARG, "cube pointer " + std::to_string(i) + " is NULL");
   if (n_cut < 1 || n_cut > c->cfg.max_batch) return host_fail(NSFRB_ERR_INVALID_ARG, "n_cut must be 1..max_batch");
   if (n_sub != kCin) return host_fail(NSFRB_ERR_UNSUPPORTED, "cutouts need 16 sub-bands (the network's input channels)");
   if (store_dtype < 0 || store_dtype > 2 || nx < 1 || ny < 1 || n_time < 1 || n_dm < 1)
     return host_fail(NSFRB_ERR_INVALID_ARG, "bad cube description");
   if (c->cfg.ny != kX) return host_fail(NSFRB_ERR_UNSUPPORTED, "cutouts are 32 x 32 pixels (classifier ny must be 32)");
   for (int i = 0; i < n_cut; ++i)
-    if (host_desc[i].dm_index < 0 || host_desc[i].dm_index >= n_dm || host_desc[i].offset < 0)
-      return host_fail(NSFRB_ERR_INVALID_ARG, "cutout descriptor out of range");
+    if (host_desc[i].dm_index < 0 || host_desc[i].dm_index >= n_dm || host_desc[i].cube < 0 ||
+        host_desc[i].cube >= n_cubes)
+      return host_fail(NSFRB_ERR_INVALID_ARG, "cutout descriptor " + std::to_string(i) + " out of range");
   hipStream_t st = (hipStream_t)stream;
   NSFRB_HIP_TRY(hipSetDevice(c->device));
   NSFRB_HIP_TRY(hipStreamSynchronize(st));   // descriptor buffers are reused across calls
@@ -299,9 +319,16 @@ extern "C" nsfrb_status nsfrb_cutouts_extract(nsfrb_classifier* c, const void* d
     NSFRB_HIP_TRY(hipMalloc((void**)&c->d_delays, sizeof(int) * n_dm * n_sub));
     c->delays_cap = n_dm * n_sub;
   }
+  if (c->cube_ptrs_cap < n_cubes) {
+    if (c->d_cube_ptrs) NSFRB_HIP_TRY(hipFree((void*)c->d_cube_ptrs));
+    c->d_cube_ptrs = nullptr;
+    NSFRB_HIP_TRY(hipMalloc((void**)&c->d_cube_ptrs, sizeof(void*) * n_cubes));
+    c->cube_ptrs_cap = n_cubes;
+  }
   NSFRB_HIP_TRY(hipMemcpy(c->d_cut_desc, host_desc, sizeof(nsfrb_cutout) * n_cut, hipMemcpyHostToDevice));
   NSFRB_HIP_TRY(hipMemcpy(c->d_delays, host_delays, sizeof(int) * n_dm * n_sub, hipMemcpyHostToDevice));
-  NSFRB_HIP_TRY(launch_cutouts(store_dtype, d_z_base, c->d_cut_desc, c->d_delays, n_cut, nx, ny, n_sub, n_time,
+  NSFRB_HIP_TRY(hipMemcpy((void*)c->d_cube_ptrs, d_z_cubes, sizeof(void*) * n_cubes, hipMemcpyHostToDevice));
+  NSFRB_HIP_TRY(launch_cutouts(store_dtype, c->d_cube_ptrs, c->d_cut_desc, c->d_delays, n_cut, nx, ny, n_sub, n_time,
                                c->cfg.n_time, (uint16_t*)d_out, st));
   return NSFRB_OK;
 }

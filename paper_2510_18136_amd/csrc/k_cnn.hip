@@ -6,7 +6,8 @@
 //
 // Network (fixed shape): input x[n][t][y][x][16] (sub-bands as channels,
 // x = 32 wide), four 3x3x3 'same' convolutions with 32 output channels and
-// ReLU, global average pool, 32->32 ReLU, 32->1 logit.
+// ReLU; head input = every channel's global maximum and its value at the
+// candidate's position (64 features); 64->32 ReLU, 32->1 logit.
 //
 // Tensors are channels-last BF16; accumulation is FP32 on the matrix cores
 // (v_mfma_f32_32x32x8_bf16: D[32x32] += A[32x8] * B[8x32]; lane l holds
@@ -187,50 +188,67 @@ __global__ void k_reduce_items(const float* __restrict__ part, int n_items, int 
 }
 
 // ------------------------------------------------------------------- head
-// h[n][c] = mean over positions of act[n][pos][c] (FP32 sums of BF16 values).
-__global__ __launch_bounds__(256) void k_pool(const uint16_t* __restrict__ act, int npos, float* __restrict__ h) {
-  __shared__ float red[256 / 32 * kCH];
+// h[n] = [m, q]: m[c] = max over positions of act[n][pos][c] (first position on
+// ties; its index goes to arg[n][c]), q[c] = act at the candidate's position.
+__global__ __launch_bounds__(256) void k_pool(const uint16_t* __restrict__ act, int npos, int centre,
+                                              float* __restrict__ h, int* __restrict__ arg) {
+  __shared__ float rv[8 * kCH];
+  __shared__ int ri[8 * kCH];
   const int n = blockIdx.x;
-  const int c = threadIdx.x % kCH, part = threadIdx.x / kCH;          // 8 parts of the positions
-  float s = 0.f;
-  for (int p = part; p < npos; p += 8) s += bf2f(act[((size_t)n * npos + p) * kCH + c]);
-  red[part * kCH + c] = s;
+  const int c = threadIdx.x % kCH, part = threadIdx.x / kCH;          // 8 interleaved parts of the positions
+  const uint16_t* a = act + (size_t)n * npos * kCH + c;
+  float best = -1.f;                                                  // activations are >= 0
+  int bi = 0;
+  for (int p = part; p < npos; p += 8) {
+    const float v = bf2f(a[(size_t)p * kCH]);
+    if (v > best) { best = v; bi = p; }                               // increasing p: first maximum kept
+  }
+  rv[part * kCH + c] = best;
+  ri[part * kCH + c] = bi;
   __syncthreads();
   if (threadIdx.x < kCH) {
-    float t = 0.f;
-    for (int k = 0; k < 8; ++k) t += red[k * kCH + threadIdx.x];
-    h[(size_t)n * kCH + threadIdx.x] = t / (float)npos;
+    float m = rv[c];
+    int mi = ri[c];
+    for (int k = 1; k < 8; ++k) {
+      const float v = rv[k * kCH + c];
+      const int i = ri[k * kCH + c];
+      if (v > m || (v == m && i < mi)) { m = v; mi = i; }
+    }
+    h[(size_t)n * 2 * kCH + c] = m;
+    h[(size_t)n * 2 * kCH + kCH + c] = bf2f(a[(size_t)centre * kCH]);
+    arg[(size_t)n * kCH + c] = mi;
   }
 }
 
-// MLP head, BCE-with-logits loss and its backward pass for a batch of n <= 1024.
-// theta_head = [W1[32][32], c1[32], w2[32], c2[1]]; grads written in the same order.
+// MLP head (64 -> 32 ReLU -> 1), BCE-with-logits loss and its backward pass for
+// a batch of n <= 1024. theta_head = [W1[32][64], c1[32], w2[32], c2[1]];
+// gradients are written in the same order.
+constexpr int kH = 2 * kCH;
 __global__ __launch_bounds__(256) void k_head(const float* __restrict__ h, const float* __restrict__ labels, int n,
                                               const float* __restrict__ th, float* __restrict__ gh,
                                               float* __restrict__ dh, float* __restrict__ logits,
                                               float* __restrict__ prob, float* __restrict__ loss_out, int backward) {
-  __shared__ float W1[kCH * kCH], c1[kCH], w2[kCH];
-  __shared__ float gW1[kCH * kCH], gc1[kCH], gw2[kCH], gc2, lsum;
-  for (int i = threadIdx.x; i < kCH * kCH; i += blockDim.x) { W1[i] = th[i]; gW1[i] = 0.f; }
+  __shared__ float W1[kCH * kH], c1[kCH], w2[kCH];
+  __shared__ float gW1[kCH * kH], gc1[kCH], gw2[kCH], gc2, lsum;
+  for (int i = threadIdx.x; i < kCH * kH; i += blockDim.x) { W1[i] = th[i]; gW1[i] = 0.f; }
   if (threadIdx.x < kCH) {
-    c1[threadIdx.x] = th[kCH * kCH + threadIdx.x];
-    w2[threadIdx.x] = th[kCH * kCH + kCH + threadIdx.x];
+    c1[threadIdx.x] = th[kCH * kH + threadIdx.x];
+    w2[threadIdx.x] = th[kCH * kH + kCH + threadIdx.x];
     gc1[threadIdx.x] = 0.f;
     gw2[threadIdx.x] = 0.f;
   }
   if (threadIdx.x == 0) { gc2 = 0.f; lsum = 0.f; }
   __syncthreads();
-  const float c2 = th[kCH * kCH + 2 * kCH];
+  const float c2 = th[kCH * kH + 2 * kCH];
   // one thread per sample: forward, loss, backward into per-sample dh; weight
-  // gradients summed with atomics in LDS (float adds of a batch; order varies
-  // only within a run of one block)
+  // gradients summed with atomics in LDS (float adds of one batch)
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    float hv[kCH], u[kCH];
-    for (int c = 0; c < kCH; ++c) hv[c] = h[(size_t)i * kCH + c];
+    const float* hv = h + (size_t)i * kH;
+    float u[kCH];
     float z = c2;
     for (int j = 0; j < kCH; ++j) {
       float s = c1[j];
-      for (int c = 0; c < kCH; ++c) s += W1[j * kCH + c] * hv[c];
+      for (int c = 0; c < kH; ++c) s += W1[j * kH + c] * hv[c];
       u[j] = s;
       z += w2[j] * fmaxf(s, 0.f);
     }
@@ -242,44 +260,49 @@ __global__ __launch_bounds__(256) void k_head(const float* __restrict__ h, const
       atomicAdd(&lsum, li / (float)n);
       const float dz = (1.0f / (1.0f + expf(-z)) - yv) / (float)n;
       atomicAdd(&gc2, dz);
-      float dhv[kCH];
-      for (int c = 0; c < kCH; ++c) dhv[c] = 0.f;
       for (int j = 0; j < kCH; ++j) {
         atomicAdd(&gw2[j], dz * fmaxf(u[j], 0.f));
-        const float du = u[j] > 0.f ? dz * w2[j] : 0.f;
-        if (du != 0.f) {
-          atomicAdd(&gc1[j], du);
-          for (int c = 0; c < kCH; ++c) {
-            atomicAdd(&gW1[j * kCH + c], du * hv[c]);
-            dhv[c] += du * W1[j * kCH + c];
-          }
+        u[j] = u[j] > 0.f ? dz * w2[j] : 0.f;                         // u now holds d(loss)/du
+        if (u[j] != 0.f) {
+          atomicAdd(&gc1[j], u[j]);
+          for (int c = 0; c < kH; ++c) atomicAdd(&gW1[j * kH + c], u[j] * hv[c]);
         }
       }
-      for (int c = 0; c < kCH; ++c) dh[(size_t)i * kCH + c] = dhv[c];
+      for (int c = 0; c < kH; ++c) {
+        float d = 0.f;
+        for (int j = 0; j < kCH; ++j) d += u[j] * W1[j * kH + c];
+        dh[(size_t)i * kH + c] = d;
+      }
     }
   }
   __syncthreads();
   if (backward) {
-    for (int i = threadIdx.x; i < kCH * kCH; i += blockDim.x) gh[i] = gW1[i];
+    for (int i = threadIdx.x; i < kCH * kH; i += blockDim.x) gh[i] = gW1[i];
     if (threadIdx.x < kCH) {
-      gh[kCH * kCH + threadIdx.x] = gc1[threadIdx.x];
-      gh[kCH * kCH + kCH + threadIdx.x] = gw2[threadIdx.x];
+      gh[kCH * kH + threadIdx.x] = gc1[threadIdx.x];
+      gh[kCH * kH + kCH + threadIdx.x] = gw2[threadIdx.x];
     }
     if (threadIdx.x == 0) {
-      gh[kCH * kCH + 2 * kCH] = gc2;
+      gh[kCH * kH + 2 * kCH] = gc2;
       loss_out[0] = lsum;
     }
   }
 }
 
-// dpre4[n][pos][c] = bf16((dh[n][c] / npos) * (act4[n][pos][c] > 0))
-__global__ void k_pool_backward(const float* __restrict__ dh, const uint16_t* __restrict__ act, int npos, long long total,
+// dpre4[n][pos][c] = bf16(g * (act4[n][pos][c] > 0)) with g = dm[n][c] at the
+// channel's maximum, + dq[n][c] at the candidate position, 0 elsewhere.
+__global__ void k_pool_backward(const float* __restrict__ dh, const int* __restrict__ arg,
+                                const uint16_t* __restrict__ act, int npos, int centre, long long total,
                                 uint16_t* __restrict__ dpre) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const int c = (int)(i % kCH);
-    const long long n = i / ((long long)npos * kCH);
-    const float g = dh[n * kCH + c] / (float)npos;
+    const long long r = i / kCH;
+    const int pos = (int)(r % npos);
+    const long long n = r / npos;
+    float g = 0.f;
+    if (pos == arg[n * kCH + c]) g = dh[n * kH + c];
+    if (pos == centre) g += dh[n * kH + kCH + c];
     dpre[i] = f2bf(bf2f(act[i]) > 0.f ? g : 0.f);
   }
 }
@@ -312,17 +335,18 @@ __global__ void k_prep_weights(const float* __restrict__ wsrc, int cin, uint16_t
 
 // ------------------------------------------------------------- cutouts
 // Dedispersion-aligned cutout around a candidate: out[k][tt][y][x][s] =
-// z[pixel (px + x - 16, py + y - 16)][s][toa - 32 + tt + delta[dm][s]], zero
-// outside the image or the series. z cubes are [n_pix][n_sub][n_t] in the
-// store dtype, cube k at z_base + desc.offset (elements).
+// z[pixel (px + x - 16, py + y - 16)][s][toa - ct/2 + tt + delta[dm][s]], zero
+// outside the image or the series. Each z cube is [n_pix][n_sub][n_t] in the
+// store dtype; descriptor k names its cube by an index into a pointer table.
 struct CutoutDesc {
-  long long offset;
+  long long cube;
   int px, py, dm, toa;
 };
 
 template <typename ST>
-__global__ void k_cutouts(const ST* __restrict__ z_base, const CutoutDesc* __restrict__ desc, const int* __restrict__ delays,
-                          int nx, int ny, int n_sub, int n_t, int ct, uint16_t* __restrict__ out, long long total) {
+__global__ void k_cutouts(const ST* const* __restrict__ cubes, const CutoutDesc* __restrict__ desc,
+                          const int* __restrict__ delays, int nx, int ny, int n_sub, int n_t, int ct,
+                          uint16_t* __restrict__ out, long long total) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const int s = (int)(i % n_sub);
@@ -336,7 +360,7 @@ __global__ void k_cutouts(const ST* __restrict__ z_base, const CutoutDesc* __res
     const int t = d.toa - ct / 2 + tt + delays[d.dm * n_sub + s];
     float v = 0.f;
     if (xi >= 0 && xi < nx && yi >= 0 && yi < ny && t >= 0 && t < n_t)
-      v = to_f32(z_base[d.offset + ((size_t)(yi * nx + xi) * n_sub + s) * n_t + t]);
+      v = to_f32(cubes[d.cube][((size_t)(yi * nx + xi) * n_sub + s) * n_t + t]);
     out[i] = f2bf(v);
   }
 }
@@ -372,8 +396,8 @@ hipError_t launch_conv_wgrad(int cin, const uint16_t* x, const uint16_t* dpre, f
   return hipGetLastError();
 }
 
-hipError_t launch_pool(const uint16_t* act, int N, int npos, float* h, hipStream_t st) {
-  hipLaunchKernelGGL(k_pool, dim3(N), dim3(256), 0, st, act, npos, h);
+hipError_t launch_pool(const uint16_t* act, int N, int npos, int centre, float* h, int* arg, hipStream_t st) {
+  hipLaunchKernelGGL(k_pool, dim3(N), dim3(256), 0, st, act, npos, centre, h, arg);
   return hipGetLastError();
 }
 
@@ -383,10 +407,11 @@ hipError_t launch_head(const float* h, const float* labels, int n, const float* 
   return hipGetLastError();
 }
 
-hipError_t launch_pool_backward(const float* dh, const uint16_t* act, int N, int npos, uint16_t* dpre, hipStream_t st) {
+hipError_t launch_pool_backward(const float* dh, const int* arg, const uint16_t* act, int N, int npos, int centre,
+                                uint16_t* dpre, hipStream_t st) {
   const long long total = (long long)N * npos * kCH;
   const unsigned grid = (unsigned)std::min<long long>((total + 255) / 256, 65536LL * 4);
-  hipLaunchKernelGGL(k_pool_backward, dim3(grid), dim3(256), 0, st, dh, act, npos, total, dpre);
+  hipLaunchKernelGGL(k_pool_backward, dim3(grid), dim3(256), 0, st, dh, arg, act, npos, centre, total, dpre);
   return hipGetLastError();
 }
 
@@ -402,20 +427,20 @@ hipError_t launch_prep_weights(const float* wsrc, int cin, uint16_t* wf, uint16_
   return hipGetLastError();
 }
 
-hipError_t launch_cutouts(int store_dtype, const void* z_base, const void* desc, const int* delays, int n_cut, int nx,
-                          int ny, int n_sub, int n_t, int ct, uint16_t* out, hipStream_t st) {
+hipError_t launch_cutouts(int store_dtype, const void* const* cubes, const void* desc, const int* delays, int n_cut,
+                          int nx, int ny, int n_sub, int n_t, int ct, uint16_t* out, hipStream_t st) {
   const long long total = (long long)n_cut * ct * kXW * kXW * n_sub;
   const unsigned grid = (unsigned)std::min<long long>((total + 255) / 256, 65536LL * 4);
   const CutoutDesc* d = (const CutoutDesc*)desc;
   if (store_dtype == DT_F32)
-    hipLaunchKernelGGL(k_cutouts<float>, dim3(grid), dim3(256), 0, st, (const float*)z_base, d, delays, nx, ny, n_sub, n_t,
-                       ct, out, total);
-  else if (store_dtype == DT_F16)
-    hipLaunchKernelGGL(k_cutouts<_Float16>, dim3(grid), dim3(256), 0, st, (const _Float16*)z_base, d, delays, nx, ny,
+    hipLaunchKernelGGL(k_cutouts<float>, dim3(grid), dim3(256), 0, st, (const float* const*)cubes, d, delays, nx, ny,
                        n_sub, n_t, ct, out, total);
+  else if (store_dtype == DT_F16)
+    hipLaunchKernelGGL(k_cutouts<_Float16>, dim3(grid), dim3(256), 0, st, (const _Float16* const*)cubes, d, delays, nx,
+                       ny, n_sub, n_t, ct, out, total);
   else
-    hipLaunchKernelGGL(k_cutouts<bf16_t>, dim3(grid), dim3(256), 0, st, (const bf16_t*)z_base, d, delays, nx, ny, n_sub,
-                       n_t, ct, out, total);
+    hipLaunchKernelGGL(k_cutouts<bf16_t>, dim3(grid), dim3(256), 0, st, (const bf16_t* const*)cubes, d, delays, nx, ny,
+                       n_sub, n_t, ct, out, total);
   return hipGetLastError();
 }
 

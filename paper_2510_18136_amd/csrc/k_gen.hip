@@ -77,6 +77,25 @@ __global__ void k_inject(T* __restrict__ cube, int layout, int n_pix, int n_sub,
   }
 }
 
+// Many boxcars at once: record r (blockIdx.y) adds amp_r to samples
+// t0_r + offsets[r][s] ... + width_r - 1 of sub-band s (blockIdx.x) of pixel
+// pixel_r of cube cube_r. Records name distinct (cube, pixel) pairs, so no two
+// blocks touch the same element.
+template <typename T>
+__global__ void k_inject_many(T* const* __restrict__ cubes, const BoxcarRec* __restrict__ recs,
+                              const int* __restrict__ offsets, int layout, int n_pix, int n_sub, int n_t) {
+  const int s = blockIdx.x;
+  const BoxcarRec r = recs[blockIdx.y];
+  T* cube = cubes[r.cube];
+  const int off = offsets[(size_t)blockIdx.y * n_sub + s];
+  for (int k = threadIdx.x; k < r.width; k += blockDim.x) {
+    const int t = r.t0 + off + k;
+    if (t < 0 || t >= n_t) continue;
+    const size_t idx = layout == 0 ? ((size_t)t * n_sub + s) * n_pix + r.pixel : ((size_t)r.pixel * n_sub + s) * n_t + t;
+    cube[idx] = from_f32<T>(to_f32(cube[idx]) + r.amp);
+  }
+}
+
 // Broadband or narrowband interference over all pixels: kind 0 adds `amp` to
 // sample t0 of every sub-band (a zero-DM spike); kind 1 adds `amp` to samples
 // t0 .. t0+len-1 of sub-band s0 (a stripe).
@@ -105,6 +124,15 @@ hipError_t launch_inject_rfi(void* cube, int dtype, int layout, int n_pix, int n
   if (dtype == DT_F32) hipLaunchKernelGGL(k_inject_rfi<float>, dim3(blocks ? blocks : 1), dim3(256), 0, st, (float*)cube, layout, n_pix, n_sub, n_t, kind, t0, len, s0, amp);
   else if (dtype == DT_F16) hipLaunchKernelGGL(k_inject_rfi<_Float16>, dim3(blocks ? blocks : 1), dim3(256), 0, st, (_Float16*)cube, layout, n_pix, n_sub, n_t, kind, t0, len, s0, amp);
   else hipLaunchKernelGGL(k_inject_rfi<bf16_t>, dim3(blocks ? blocks : 1), dim3(256), 0, st, (bf16_t*)cube, layout, n_pix, n_sub, n_t, kind, t0, len, s0, amp);
+  return hipGetLastError();
+}
+
+hipError_t launch_inject_many(void* const* cubes, int dtype, int layout, int n_pix, int n_sub, int n_t,
+                              const BoxcarRec* recs, const int* offsets, int n, hipStream_t st) {
+  const dim3 grid(n_sub, n);
+  if (dtype == DT_F32) hipLaunchKernelGGL(k_inject_many<float>, grid, dim3(256), 0, st, (float* const*)cubes, recs, offsets, layout, n_pix, n_sub, n_t);
+  else if (dtype == DT_F16) hipLaunchKernelGGL(k_inject_many<_Float16>, grid, dim3(256), 0, st, (_Float16* const*)cubes, recs, offsets, layout, n_pix, n_sub, n_t);
+  else hipLaunchKernelGGL(k_inject_many<bf16_t>, grid, dim3(256), 0, st, (bf16_t* const*)cubes, recs, offsets, layout, n_pix, n_sub, n_t);
   return hipGetLastError();
 }
 

@@ -759,6 +759,14 @@ extern "C" nsfrb_status nsfrb_zcube_get(nsfrb_search* h, void* host_out) {
   return NSFRB_OK;
 }
 
+extern "C" nsfrb_status nsfrb_zcube_device(nsfrb_search* h, const void** d_z) {
+  g_last_error.clear();
+  if (!h || !d_z) return fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  if (!h->last_z) return fail(NSFRB_ERR_NOT_READY, "no run has been enqueued on this handle");
+  *d_z = h->last_z;
+  return NSFRB_OK;
+}
+
 extern "C" nsfrb_status nsfrb_flag_count_get(nsfrb_search* h, int64_t* count) {
   g_last_error.clear();
   nsfrb_status st = wait_run(h);
@@ -1041,6 +1049,23 @@ extern "C" nsfrb_status nsfrb_batch_maps_get(nsfrb_batch* b, int32_t cube, float
   return nsfrb_maps_get(h, snr_max, toa);
 }
 
+extern "C" nsfrb_status nsfrb_batch_best_get(nsfrb_batch* b, int32_t cube, float* snr, int32_t* dm_index,
+                                             int32_t* width_index, int32_t* toa) {
+  g_last_error.clear();
+  nsfrb_search* h = nullptr;
+  nsfrb_status st = batch_cube(b, cube, &h);
+  if (st != NSFRB_OK) return st;
+  return nsfrb_best_get(h, snr, dm_index, width_index, toa);
+}
+
+extern "C" nsfrb_status nsfrb_batch_zcube_device(nsfrb_batch* b, int32_t cube, const void** d_z) {
+  g_last_error.clear();
+  nsfrb_search* h = nullptr;
+  nsfrb_status st = batch_cube(b, cube, &h);
+  if (st != NSFRB_OK) return st;
+  return nsfrb_zcube_device(h, d_z);
+}
+
 extern "C" nsfrb_status nsfrb_batch_info_get(nsfrb_batch* b, int64_t* info) {
   g_last_error.clear();
   if (!b || !info) return fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
@@ -1082,6 +1107,43 @@ extern "C" nsfrb_status nsfrb_inject_boxcar(void* d_cube, int32_t dtype, int32_t
   HIP_TRY(hipMemcpy(d_off, host_offsets, sizeof(int) * n_sub, hipMemcpyHostToDevice));
   HIP_TRY(launch_inject(d_cube, dtype, layout, n_pix, n_sub, n_time, pixel, t0, width, amp, d_off,
                         (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_inject_boxcars(void* const* d_cubes, int32_t n_cubes, int32_t dtype, int32_t layout,
+                                             int32_t n_pix, int32_t n_sub, int32_t n_time,
+                                             const nsfrb_boxcar* host_boxcars, const int32_t* host_offsets,
+                                             int32_t n, void* stream) {
+  static_assert(sizeof(nsfrb_boxcar) == sizeof(BoxcarRec), "nsfrb_boxcar layout");
+  g_last_error.clear();
+  if (!d_cubes || n_cubes < 1 || !host_boxcars || !host_offsets || n < 1 || dtype < 0 || dtype > 2 ||
+      (layout != 0 && layout != 1) || n_pix < 1 || n_sub < 1 || n_time < 1 || n > 65535)
+    return fail(NSFRB_ERR_INVALID_ARG, "bad injection arguments");
+  for (int i = 0; i < n_cubes; ++i)
+    if (!d_cubes[i]) return fail(NSFRB_ERR_INVALID_ARG, "cube pointer " + std::to_string(i) + " is NULL");
+  std::vector<long long> keys((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    const nsfrb_boxcar& b = host_boxcars[i];
+    if (b.cube < 0 || b.cube >= n_cubes || b.pixel < 0 || b.pixel >= n_pix || b.width < 1 || !std::isfinite(b.amp))
+      return fail(NSFRB_ERR_INVALID_ARG, "boxcar " + std::to_string(i) + " out of range");
+    keys[(size_t)i] = (long long)b.cube * n_pix + b.pixel;
+  }
+  std::sort(keys.begin(), keys.end());
+  if (std::adjacent_find(keys.begin(), keys.end()) != keys.end())
+    return fail(NSFRB_ERR_INVALID_ARG, "two boxcars share a (cube, pixel)");
+  // a utility for building inputs: synchronous, so host arrays can be released on return
+  const size_t bytes_ptr = sizeof(void*) * n_cubes, bytes_rec = sizeof(BoxcarRec) * n,
+               bytes_off = sizeof(int) * (size_t)n * n_sub;
+  char* d_buf = nullptr;
+  HIP_TRY(hipMalloc((void**)&d_buf, bytes_ptr + bytes_rec + bytes_off));
+  std::unique_ptr<void, hipError_t (*)(void*)> guard(d_buf, hipFree);
+  HIP_TRY(hipMemcpy(d_buf, d_cubes, bytes_ptr, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_buf + bytes_ptr, host_boxcars, bytes_rec, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d_buf + bytes_ptr + bytes_rec, host_offsets, bytes_off, hipMemcpyHostToDevice));
+  HIP_TRY(launch_inject_many((void* const*)d_buf, dtype, layout, n_pix, n_sub, n_time,
+                             (const BoxcarRec*)(d_buf + bytes_ptr), (const int*)(d_buf + bytes_ptr + bytes_rec), n,
+                             (hipStream_t)stream));
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   return NSFRB_OK;
 }

@@ -66,6 +66,13 @@ hipError_t launch_inject(void* cube, int dtype, int layout, int n_pix, int n_sub
 }  // namespace nsfrb
 
 namespace nsfrb {
+// One boxcar injection (layout of nsfrb_boxcar in the C ABI).
+struct BoxcarRec {
+  int cube, pixel, t0, width;
+  float amp;
+};
+hipError_t launch_inject_many(void* const* cubes, int dtype, int layout, int n_pix, int n_sub, int n_t,
+                              const BoxcarRec* recs, const int* offsets, int n, hipStream_t st);
 hipError_t launch_inject_rfi(void* cube, int dtype, int layout, int n_pix, int n_sub, int n_t, int kind, int t0, int len,
                              int s0, float amp, hipStream_t st);
 // classifier kernels (k_cnn.hip)
@@ -76,13 +83,14 @@ hipError_t launch_conv_bwd_data(const uint16_t* dpre, const uint16_t* wb, const 
 int wgrad_items(int N, int T);
 hipError_t launch_conv_wgrad(int cin, const uint16_t* x, const uint16_t* dpre, float* part, float* part_db, float* dw,
                              float* db, int N, int T, int Y, hipStream_t st);
-hipError_t launch_pool(const uint16_t* act, int N, int npos, float* h, hipStream_t st);
+hipError_t launch_pool(const uint16_t* act, int N, int npos, int centre, float* h, int* arg, hipStream_t st);
 hipError_t launch_head(const float* h, const float* labels, int n, const float* th, float* gh, float* dh, float* logits,
                        float* prob, float* loss, int backward, hipStream_t st);
-hipError_t launch_pool_backward(const float* dh, const uint16_t* act, int N, int npos, uint16_t* dpre, hipStream_t st);
+hipError_t launch_pool_backward(const float* dh, const int* arg, const uint16_t* act, int N, int npos, int centre,
+                                uint16_t* dpre, hipStream_t st);
 hipError_t launch_adam(float* th, float* m, float* v, const float* g, int n, float lr, float b1, float b2, float eps,
                        float bc1, float bc2, hipStream_t st);
 hipError_t launch_prep_weights(const float* wsrc, int cin, uint16_t* wf, uint16_t* wb, hipStream_t st);
-hipError_t launch_cutouts(int store_dtype, const void* z_base, const void* desc, const int* delays, int n_cut, int nx,
-                          int ny, int n_sub, int n_t, int ct, uint16_t* out, hipStream_t st);
+hipError_t launch_cutouts(int store_dtype, const void* const* cubes, const void* desc, const int* delays, int n_cut,
+                          int nx, int ny, int n_sub, int n_t, int ct, uint16_t* out, hipStream_t st);
 }  // namespace nsfrb

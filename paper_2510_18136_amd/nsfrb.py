@@ -3,7 +3,9 @@
 Every step of the search runs in the HIP library libnsfrb.so. PyTorch, when
 used by a caller, only provides device buffers and streams: pass
 `tensor.data_ptr()` and `torch.cuda.current_stream().cuda_stream`.
-Loading fails loudly when the library has not been built.
+Loading fails loudly when the library has not been built. A process that
+uses both should import torch and touch its device (torch.cuda.is_available())
+before the first library call, so that both share the HIP runtime torch loads.
 """
 import ctypes
 import os
@@ -26,13 +28,15 @@ EXPORTS = [
     "nsfrb_version", "nsfrb_last_error", "nsfrb_config_validate", "nsfrb_plan_delays",
     "nsfrb_search_create", "nsfrb_search_destroy", "nsfrb_search_run", "nsfrb_candidates_get",
     "nsfrb_delay_table_get", "nsfrb_maps_get", "nsfrb_best_get", "nsfrb_noise_stats_get",
-    "nsfrb_noise_stats_set", "nsfrb_zcube_get", "nsfrb_flag_count_get", "nsfrb_maps_device",
+    "nsfrb_noise_stats_set", "nsfrb_zcube_get", "nsfrb_zcube_device", "nsfrb_flag_count_get", "nsfrb_maps_device",
     "nsfrb_profiling_enable", "nsfrb_stage_times_get", "nsfrb_search_plan_info",
     "nsfrb_batch_create", "nsfrb_batch_destroy", "nsfrb_batch_run", "nsfrb_batch_run_separate",
-    "nsfrb_batch_use_graph", "nsfrb_batch_candidates_get", "nsfrb_batch_maps_get", "nsfrb_batch_info_get",
-    "nsfrb_generate_noise", "nsfrb_inject_boxcar", "nsfrb_philox_fill", "nsfrb_inject_rfi",
+    "nsfrb_batch_use_graph", "nsfrb_batch_candidates_get", "nsfrb_batch_maps_get", "nsfrb_batch_best_get",
+    "nsfrb_batch_zcube_device", "nsfrb_batch_info_get",
+    "nsfrb_generate_noise", "nsfrb_inject_boxcar", "nsfrb_inject_boxcars", "nsfrb_philox_fill", "nsfrb_inject_rfi",
     "nsfrb_classifier_param_count", "nsfrb_classifier_create", "nsfrb_classifier_destroy",
-    "nsfrb_classifier_params_get", "nsfrb_classifier_params_set", "nsfrb_classifier_grads_get",
+    "nsfrb_classifier_params_get", "nsfrb_classifier_params_set", "nsfrb_classifier_set_lr",
+    "nsfrb_classifier_grads_get",
     "nsfrb_classifier_train_step", "nsfrb_classifier_infer", "nsfrb_cutouts_extract",
 ]
 
@@ -64,8 +68,13 @@ class ClassifierConfig(ctypes.Structure):
                 ("device", ctypes.c_int32)]
 
 
+class Boxcar(ctypes.Structure):
+    _fields_ = [("cube", ctypes.c_int32), ("pixel", ctypes.c_int32), ("t0", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("amp", ctypes.c_float)]
+
+
 class CutoutDesc(ctypes.Structure):
-    _fields_ = [("offset", ctypes.c_int64), ("px", ctypes.c_int32), ("py", ctypes.c_int32),
+    _fields_ = [("cube", ctypes.c_int64), ("px", ctypes.c_int32), ("py", ctypes.c_int32),
                 ("dm_index", ctypes.c_int32), ("toa", ctypes.c_int32)]
 
 
@@ -102,6 +111,7 @@ def lib():
             "nsfrb_noise_stats_get": ([vp, pd, pd], ctypes.c_int),
             "nsfrb_noise_stats_set": ([vp, pd, pd], ctypes.c_int),
             "nsfrb_zcube_get": ([vp, vp], ctypes.c_int),
+            "nsfrb_zcube_device": ([vp, ctypes.POINTER(vp)], ctypes.c_int),
             "nsfrb_flag_count_get": ([vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
             "nsfrb_maps_device": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp)], ctypes.c_int),
             "nsfrb_profiling_enable": ([vp, i32], ctypes.c_int),
@@ -115,11 +125,15 @@ def lib():
             "nsfrb_batch_use_graph": ([vp, i32], ctypes.c_int),
             "nsfrb_batch_candidates_get": ([vp, i32, ctypes.POINTER(Candidate), i32, pi32, pi32], ctypes.c_int),
             "nsfrb_batch_maps_get": ([vp, i32, pf, pi32], ctypes.c_int),
+            "nsfrb_batch_best_get": ([vp, i32, pf, pi32, pi32, pi32], ctypes.c_int),
+            "nsfrb_batch_zcube_device": ([vp, i32, ctypes.POINTER(vp)], ctypes.c_int),
             "nsfrb_batch_info_get": ([vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
             "nsfrb_generate_noise": ([vp, i32, i32, i32, i32, i32, ctypes.c_uint64, ctypes.c_float, vp],
                                      ctypes.c_int),
             "nsfrb_inject_boxcar": ([vp, i32, i32, i32, i32, i32, i32, i32, i32, ctypes.c_float, pi32, vp],
                                     ctypes.c_int),
+            "nsfrb_inject_boxcars": ([ctypes.POINTER(vp), i32, i32, i32, i32, i32, i32, ctypes.POINTER(Boxcar),
+                                      pi32, i32, vp], ctypes.c_int),
             "nsfrb_philox_fill": ([vp, ctypes.c_int64, ctypes.c_uint64, vp], ctypes.c_int),
             "nsfrb_inject_rfi": ([vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, ctypes.c_float, vp], ctypes.c_int),
             "nsfrb_classifier_param_count": ([], ctypes.c_int32),
@@ -128,10 +142,11 @@ def lib():
             "nsfrb_classifier_params_get": ([vp, pf], ctypes.c_int),
             "nsfrb_classifier_params_set": ([vp, pf], ctypes.c_int),
             "nsfrb_classifier_grads_get": ([vp, pf], ctypes.c_int),
+            "nsfrb_classifier_set_lr": ([vp, ctypes.c_float], ctypes.c_int),
             "nsfrb_classifier_train_step": ([vp, vp, vp, i32, i32, pf, vp], ctypes.c_int),
             "nsfrb_classifier_infer": ([vp, vp, i32, vp, vp], ctypes.c_int),
-            "nsfrb_cutouts_extract": ([vp, vp, i32, i32, i32, i32, i32, pi32, i32, ctypes.POINTER(CutoutDesc),
-                                       i32, vp, vp], ctypes.c_int),
+            "nsfrb_cutouts_extract": ([vp, ctypes.POINTER(vp), i32, i32, i32, i32, i32, i32, pi32, i32,
+                                       ctypes.POINTER(CutoutDesc), i32, vp, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -289,6 +304,12 @@ class Search:
             vals = raw.astype(np.float64)
         return vals.reshape(c.n_pix, c.n_sub, c.n_time), raw.reshape(c.n_pix, c.n_sub, c.n_time)
 
+    def zcube_device(self):
+        """Device address of the normalised cube of the last run (no wait)."""
+        p = ctypes.c_void_p()
+        check(lib().nsfrb_zcube_device(self.h, ctypes.byref(p)))
+        return int(p.value)
+
     def flag_count(self):
         v = ctypes.c_int64()
         check(lib().nsfrb_flag_count_get(self.h, ctypes.byref(v)))
@@ -372,6 +393,19 @@ class Batch:
         check(lib().nsfrb_batch_maps_get(self.h, i, _ptr(snr, ctypes.c_float), _ptr(toa, ctypes.c_int32)))
         return snr, toa
 
+    def best(self, i):
+        n = self.cfgs[i].n_pix
+        s = np.zeros(n, np.float32)
+        d, w, t = (np.zeros(n, np.int32) for _ in range(3))
+        check(lib().nsfrb_batch_best_get(self.h, i, _ptr(s, ctypes.c_float), _ptr(d, ctypes.c_int32),
+                                         _ptr(w, ctypes.c_int32), _ptr(t, ctypes.c_int32)))
+        return s, d, w, t
+
+    def zcube_device(self, i):
+        p = ctypes.c_void_p()
+        check(lib().nsfrb_batch_zcube_device(self.h, i, ctypes.byref(p)))
+        return int(p.value)
+
     def info(self):
         out = np.zeros(5, np.int64)
         check(lib().nsfrb_batch_info_get(self.h, _ptr(out, ctypes.c_int64)))
@@ -390,6 +424,17 @@ def inject_boxcar(d_ptr, dtype, layout, n_pix, n_sub, n_time, pixel, t0, width, 
     check(lib().nsfrb_inject_boxcar(ctypes.c_void_p(int(d_ptr)), DTYPES[dtype], LAYOUTS[layout], n_pix, n_sub,
                                     n_time, int(pixel), int(t0), int(width), float(amp), _ptr(off, ctypes.c_int32),
                                     ctypes.c_void_p(int(stream))))
+
+
+def inject_boxcars(d_ptrs, dtype, layout, n_pix, n_sub, n_time, boxcars, offsets, stream=0):
+    """boxcars: (cube, pixel, t0, width, amp) tuples; offsets: [n][n_sub] sample shifts."""
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    n = len(boxcars)
+    assert off.shape == (n, n_sub)
+    ptrs = (ctypes.c_void_p * len(d_ptrs))(*[ctypes.c_void_p(int(p)) for p in d_ptrs])
+    recs = (Boxcar * n)(*[Boxcar(int(k), int(p), int(t), int(w), float(a)) for (k, p, t, w, a) in boxcars])
+    check(lib().nsfrb_inject_boxcars(ptrs, len(d_ptrs), DTYPES[dtype], LAYOUTS[layout], n_pix, n_sub, n_time, recs,
+                                     _ptr(off, ctypes.c_int32), n, ctypes.c_void_p(int(stream))))
 
 
 def philox_fill(d_ptr, n_blocks, seed, stream=0):
@@ -447,6 +492,9 @@ class Classifier:
         assert t.size == self.n_params
         check(lib().nsfrb_classifier_params_set(self.h, _ptr(t, ctypes.c_float)))
 
+    def set_lr(self, lr):
+        check(lib().nsfrb_classifier_set_lr(self.h, float(lr)))
+
     def grads(self):
         out = np.zeros(self.n_params, np.float32)
         check(lib().nsfrb_classifier_grads_get(self.h, _ptr(out, ctypes.c_float)))
@@ -464,11 +512,12 @@ class Classifier:
         check(lib().nsfrb_classifier_infer(self.h, ctypes.c_void_p(int(d_cutouts)), int(n),
                                            ctypes.c_void_p(int(d_prob)), ctypes.c_void_p(int(stream))))
 
-    def cutouts(self, d_z_base, store_dtype, nx, ny, n_sub, n_time, delays, descs, d_out, stream=0):
-        """descs: list of (offset, px, py, dm_index, toa)."""
+    def cutouts(self, d_z_cubes, store_dtype, nx, ny, n_sub, n_time, delays, descs, d_out, stream=0):
+        """d_z_cubes: device addresses of the cubes; descs: (cube, px, py, dm_index, toa) tuples."""
         dl = np.ascontiguousarray(delays, dtype=np.int32)
-        arr = (CutoutDesc * len(descs))(*[CutoutDesc(int(o), int(x), int(y), int(d), int(t))
-                                            for (o, x, y, d, t) in descs])
-        check(lib().nsfrb_cutouts_extract(self.h, ctypes.c_void_p(int(d_z_base)), DTYPES[store_dtype], int(nx),
-                                          int(ny), int(n_sub), int(n_time), _ptr(dl, ctypes.c_int32), dl.shape[0],
+        ptrs = (ctypes.c_void_p * len(d_z_cubes))(*[ctypes.c_void_p(int(p)) for p in d_z_cubes])
+        arr = (CutoutDesc * len(descs))(*[CutoutDesc(int(k), int(x), int(y), int(d), int(t))
+                                            for (k, x, y, d, t) in descs])
+        check(lib().nsfrb_cutouts_extract(self.h, ptrs, len(d_z_cubes), DTYPES[store_dtype], int(nx), int(ny),
+                                          int(n_sub), int(n_time), _ptr(dl, ctypes.c_int32), dl.shape[0],
                                           arr, len(descs), ctypes.c_void_p(int(d_out)), ctypes.c_void_p(int(stream))))

@@ -138,3 +138,39 @@ def test_batch_matches_oracle_on_small_cubes():
             clear = fin & (o["margin"] > 2e-4)
             assert np.array_equal(toa[clear], o["toa"][clear])
             assert ntot == o["n_total"]
+
+
+def test_injectors_match_their_definition():
+    """Batched boxcars and interference added to zero cubes equal the definition
+    written out in NumPy (FP32 adds to zero are exact), in both layouts."""
+    rng = np.random.default_rng(11)
+    n_pix, n_sub, n_t = 37, 16, 90
+    for layout in ("tsp", "pst"):
+        cubes = [torch.zeros(n_pix * n_sub * n_t, dtype=torch.float32, device="cuda") for _ in range(3)]
+        ptrs = [c.data_ptr() for c in cubes]
+        boxcars = [(0, 5, 10, 4, 1.5), (2, 5, 80, 16, -2.25), (2, 36, -3, 7, 0.75), (1, 0, 0, 1, 3.0)]
+        offsets = rng.integers(0, 9, (len(boxcars), n_sub))
+        print(f"[gpu] inject_boxcars layout={layout}", flush=True)
+        nsfrb.inject_boxcars(ptrs, "f32", layout, n_pix, n_sub, n_t, boxcars, offsets)
+        nsfrb.inject_rfi(ptrs[1], "f32", layout, n_pix, n_sub, n_t, "spike", 33, 1, 0, 0.5)
+        nsfrb.inject_rfi(ptrs[1], "f32", layout, n_pix, n_sub, n_t, "stripe", 85, 20, 3, 0.25)
+        torch.cuda.synchronize()
+        want = np.zeros((3, n_t, n_sub, n_pix), np.float32)            # [cube][t][s][p]
+        for (k, p, t0, w, a), off in zip(boxcars, offsets):
+            for s in range(n_sub):
+                for t in range(t0 + off[s], t0 + off[s] + w):
+                    if 0 <= t < n_t:
+                        want[k, t, s, p] += np.float32(a)
+        want[1, 33, :, :] += np.float32(0.5)
+        want[1, 85:, 3, :] += np.float32(0.25)
+        for k in range(3):
+            got = cubes[k].cpu().numpy()
+            got = got.reshape(n_t, n_sub, n_pix) if layout == "tsp" else got.reshape(n_pix, n_sub, n_t).transpose(2, 1, 0)
+            assert np.array_equal(got, want[k]), (layout, k)
+
+
+def test_inject_boxcars_rejects_shared_pixels():
+    cube = torch.zeros(4 * 2 * 8, dtype=torch.float32, device="cuda")
+    with pytest.raises(nsfrb.NsfrbError):
+        nsfrb.inject_boxcars([cube.data_ptr()], "f32", "tsp", 4, 2, 8, [(0, 1, 0, 1, 1.0), (0, 1, 3, 1, 1.0)],
+                             np.zeros((2, 2), np.int32))

@@ -107,17 +107,16 @@ def test_cutouts_match_definition():
     freqs = np.linspace(1.311, 1.499, ns)
     delays = delay_table(freqs, freqs.max(), 134.2, np.linspace(0, 1000, 8))
     cubes = [rng.standard_normal((nx * ny, ns, nt)).astype(np.float16) for _ in range(2)]
-    base = np.concatenate([c.ravel() for c in cubes])
-    zd = torch.from_numpy(base).cuda()
-    descs = [(0, 3, 37, 5, 40), (cubes[0].size, 20, 20, 7, 130), (cubes[0].size, 0, 0, 0, 10)]
+    zd = [torch.from_numpy(c.ravel()).cuda() for c in cubes]
+    descs = [(0, 3, 37, 5, 40), (1, 20, 20, 7, 130), (1, 0, 0, 0, 10), (0, 39, 0, 3, 150)]
     out = torch.zeros(len(descs) * ct * 32 * 32 * 16, dtype=torch.int16, device="cuda")
     with nsfrb.Classifier(max_batch=4, n_time=ct, ny=32) as c:
-        c.cutouts(zd.data_ptr(), "f16", nx, ny, ns, nt, delays, descs, out.data_ptr(),
+        c.cutouts([z.data_ptr() for z in zd], "f16", nx, ny, ns, nt, delays, descs, out.data_ptr(),
                   stream=torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
     got = (out.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32).reshape(len(descs), ct, 32, 32, 16)
-    for k, (off, px, py, d, toa) in enumerate(descs):
-        z = cubes[0] if off == 0 else cubes[1]
+    for k, (cube, px, py, d, toa) in enumerate(descs):
+        z = cubes[cube]
         ref = np.zeros((ct, 32, 32, 16), np.float32)
         for tt in range(ct):
             for y in range(32):

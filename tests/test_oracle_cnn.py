@@ -17,7 +17,41 @@ def tiny(seed, n=2, T=3, Y=3, X=4):
 
 
 def test_parameter_count():
-    assert cnn.n_params() == 97985
+    # 4 conv layers (27 taps x cin x 32 + 32) + fc1 64 -> 32 + fc2 32 -> 1
+    assert cnn.n_params() == (27 * 16 * 32 + 32) + 3 * (27 * 32 * 32 + 32) + (64 * 32 + 32) + (32 + 1) == 99009
+
+
+def test_head_features_by_brute_force():
+    """h = [per-channel maximum (first position on ties), features at the centre]."""
+    x, theta, _ = tiny(8, n=2, T=4, Y=4, X=6)
+    f = cnn.forward(theta, x)
+    a4 = f["acts"][4]
+    n, T, Y, X, C = a4.shape
+    for i in range(n):
+        for c in range(C):
+            best, pos = -np.inf, None
+            for t in range(T):
+                for y in range(Y):
+                    for xx in range(X):
+                        if a4[i, t, y, xx, c] > best:
+                            best, pos = a4[i, t, y, xx, c], (t * Y + y) * X + xx
+            assert f["h"][i, c] == best and f["arg"][i, c] == pos
+            assert f["h"][i, C + c] == a4[i, 2, 2, 3, c]
+
+
+def test_pool_backward_ties_go_to_the_first_position():
+    a4 = np.zeros((1, 2, 2, 2, 3))
+    a4[0, 0, 1, 1, 0] = a4[0, 1, 0, 0, 0] = 2.0            # tie in channel 0
+    a4[0, 1, 1, 1, 1] = 1.0
+    flat = a4.reshape(1, 8, 3)
+    arg = np.argmax(flat, axis=1)
+    d = cnn.pool_backward(a4.shape, arg, np.arange(1.0, 7.0)[None, :])
+    want = np.zeros_like(a4)
+    want[0, 0, 1, 1, 0] += 1.0                                # first of the tied maxima, (t, y, x) order
+    want[0, 1, 1, 1, 1] += 2.0
+    want[0, 0, 0, 0, 2] += 3.0                                # all-equal channel: position 0
+    want[0, 1, 1, 1, :] += [4.0, 5.0, 6.0]                    # centre (T/2, Y/2, X/2) = (1, 1, 1)
+    np.testing.assert_array_equal(d, want)
 
 
 def test_conv_matches_brute_force_and_scipy():
@@ -74,34 +108,24 @@ def test_gradient_matches_central_differences(seed):
 
 
 def test_input_gradient_through_all_layers():
-    """d loss / d x via the chain of conv backward passes, against differences."""
+    """d loss / d x through the head, the pool and every conv backward pass, against differences."""
     x, theta, labels = tiny(3, n=1)
-    P = cnn.unpack(theta)
-    f = cnn.forward(theta, x)
-    loss0 = cnn.bce_logits(f["z"], labels)
+    _, _, _, dx = cnn.loss_and_grad(theta, x, labels, input_grad=True)
 
     def loss_at(xx):
         return cnn.bce_logits(cnn.forward(theta, xx)["z"], labels)
 
-    # analytic dx: rerun the backward keeping the layer-1 input gradient
-    y = labels
-    dz = (1 / (1 + np.exp(-f["z"])) - y) / y.size
-    du = np.outer(dz, P[10]) * (f["u"] > 0)
-    dh = du @ P[8]
-    a4 = f["acts"][4]
-    dpost = np.broadcast_to((dh / np.prod(a4.shape[1:4]))[:, None, None, None, :], a4.shape)
-    for l in (3, 2, 1, 0):
-        dpre = dpost * (f["acts"][l + 1] > 0)
-        _, _, dpost = cnn.conv3_backward(f["acts"][l], P[2 * l], dpre, need_dx=True)
     rng = np.random.default_rng(4)
-    for _ in range(6):
+    checked = 0
+    for _ in range(40):
         i = tuple(rng.integers(0, s) for s in x.shape)
         xp, xm = x.copy(), x.copy()
-        xp[i] += 1e-5
-        xm[i] -= 1e-5
-        num = (loss_at(xp) - loss_at(xm)) / 2e-5
-        assert abs(num - dpost[i]) <= 1e-7 + 1e-5 * abs(num)
-    assert np.isfinite(loss0)
+        xp[i] += 1e-6
+        xm[i] -= 1e-6
+        num = (loss_at(xp) - loss_at(xm)) / 2e-6
+        assert abs(num - dx[i]) <= 1e-7 + 1e-5 * abs(num), (i, num, dx[i])
+        checked += dx[i] != 0
+    assert checked >= 5                          # the path reaches the input
 
 
 def test_bf16_rounding_points_change_little():
