@@ -57,7 +57,10 @@ def round_f32_to_bf16(x32):
 
 
 def cast_store(z64, store):
-    """FP64 -> stored dtype; returns the stored values as exact float64."""
+    """FP64 -> stored dtype; returns the stored values as exact float64.
+    store "f64" keeps z unquantised (the reference for the precision forms)."""
+    if store == "f64":
+        return np.asarray(z64, dtype=np.float64)
     z32 = np.asarray(z64, dtype=np.float64).astype(np.float32)
     if store == "f32":
         return z32.astype(np.float64)

@@ -155,3 +155,12 @@ def test_config1_pulse_has_expected_snr_and_no_candidates():
     assert 2.0 < r["snr_max"][3, 2, p] < 7.0
     np.testing.assert_array_equal(r["delays"], np.loadtxt(
         __file__.replace("test_oracle_search.py", "golden/delays_c1.txt"), dtype=np.int64)[:, 1:])
+
+
+def test_unquantised_store_keeps_fp64_values():
+    rng = np.random.default_rng(12)
+    z = rng.standard_normal((5, 3, 7)) * 1e-3 + 1.0 / 3.0
+    assert np.array_equal(osr.cast_store(z, "f64"), z)
+    assert not np.array_equal(osr.cast_store(z, "f32"), z)
+    # the FP32 store differs from the unquantised one by at most half an FP32 ulp per value
+    assert np.abs(osr.cast_store(z, "f32") - z).max() <= 2.0 ** -25
