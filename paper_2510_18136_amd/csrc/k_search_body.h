@@ -18,9 +18,12 @@
 //    past the end of a de-dispersed series sums to -inf and is never a maximum;
 //  * kWaves/PIX waves share a pixel and split its DM trials round-robin (the
 //    "DM chunk" of a wave is every (kWaves/PIX)-th trial);
-//  * lane l holds the C consecutive samples t = C*l + c (C is odd, so lanes hit
-//    distinct LDS banks at any delay);
-//  * D_d[t] = sum_s z[s][t + delta[d][s]] is formed in registers (FP32);
+//  * lane l holds the C consecutive samples t = C*l + c (FP32 rows: C odd, so
+//    lanes hit distinct LDS banks at any delay; FP16 rows: C even with C/2
+//    odd, read as dwords holding two samples);
+//  * D_d[t] = sum_s z[s][t + delta[d][s]] is formed in registers (FP32); an
+//    FP16 sample is added by v_fma_mix_f32 (f16 operand * 1.0 + f32), one
+//    rounding, the same result as converting and then adding;
 //  * boxcars use the pairwise doubling B_2w[t] = B_w[t] + B_w[t+w]; a width
 //    that is not a power of two is the sum of the power-of-two windows of its
 //    binary digits placed end to end. Each output is a balanced sum, so the
@@ -73,21 +76,67 @@ __device__ __forceinline__ void copy_arr(float (&out)[C], const float (&a)[C]) {
   for (int c = 0; c < C; ++c) out[c] = a[c];
 }
 
+// acc + (FP16 sample in the low / high half of w), rounded once.
+__device__ __forceinline__ float add_f16_lo(float acc, uint32_t w) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(acc));
+  return r;
+}
+__device__ __forceinline__ float add_f16_hi(float acc, uint32_t w) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(acc));
+  return r;
+}
+
+// cur[c] += row[e0 + c] for c < C, e0 = delay + C * lane.
+template <int C, typename T>
+__device__ __forceinline__ void add_row(float (&cur)[C], const T* row, int dl, int l) {
+  const T* r = row + dl + C * l;
+#pragma unroll
+  for (int c = 0; c < C; ++c) cur[c] += to_f32(r[c]);
+}
+// FP16 rows (row start dword-aligned, C even): the samples of a lane start at
+// element e0 = dl + C*l, whose parity is that of dl (uniform); dword k of the
+// lane holds elements (2k, 2k+1) counted from e0 rounded down to even.
+template <int C>
+__device__ __forceinline__ void add_row(float (&cur)[C], const _Float16* row, int dl, int l) {
+  static_assert((C & 1) == 0, "FP16 rows need an even number of samples per lane");
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(row) + ((dl + C * l) >> 1);
+  if (dl & 1) {
+    cur[0] = add_f16_hi(cur[0], w[0]);
+#pragma unroll
+    for (int k = 0; k < C / 2; ++k) {
+      const uint32_t v = w[k + 1];
+      cur[2 * k + 1] = add_f16_lo(cur[2 * k + 1], v);
+      if (2 * k + 2 < C) cur[2 * k + 2] = add_f16_hi(cur[2 * k + 2], v);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < C / 2; ++k) {
+      const uint32_t v = w[k];
+      cur[2 * k] = add_f16_lo(cur[2 * k], v);
+      cur[2 * k + 1] = add_f16_hi(cur[2 * k + 1], v);
+    }
+  }
+}
+
 struct Best {
   float s;
   int d, w, t;
 };
 
+// (s, d, w) beats b: higher S/N, then the smaller DM index, then the smaller
+// width index (written without branches, so the reporting code stays in one
+// basic block with the boxcar arithmetic around it).
 __device__ __forceinline__ bool better(float s, int d, int w, const Best& b) {
-  if (s > b.s) return true;
-  if (s < b.s || !(s == b.s)) return false;
-  return d < b.d || (d == b.d && w < b.w);
+  return (s > b.s) | ((s == b.s) & ((d < b.d) | ((d == b.d) & (w < b.w))));
 }
 
 // Max over all samples of a boxcar array and the first sample reaching it:
-// lane maxima by a max3 tree, the wave maximum by DPP, the first lane holding
-// it by a ballot, and the first register of that lane holding it from a
-// per-lane index (two VALU ops per register) read from that lane.
+// lane maxima by a max3 tree over groups of three registers, the wave maximum
+// by DPP, the first lane L holding it by a ballot, then the first register of
+// lane L holding it from one ballot per register (compares write lane masks
+// to scalar registers; the lane's bit is tested on the scalar unit).
 template <int C>
 __device__ __forceinline__ void max_first(const float (&b)[C], float& M, int& T) {
   constexpr int G = (C + 2) / 3;
@@ -103,12 +152,13 @@ __device__ __forceinline__ void max_first(const float (&b)[C], float& M, int& T)
 #pragma unroll
   for (int k = 1; k < G; k += 2) m = (k + 1 < G) ? fmaxf(m, fmaxf(g[k], g[k + 1])) : fmaxf(m, g[k]);
   M = wave_max_f(m);
-  if (!(M > kNegInf)) { T = -1; return; }
+  // some lane's maximum equals M, so the ballot is never empty
   const int L = __ffsll((long long)ballot(m == M)) - 1;
-  int cidx = C;
+  const uint64_t bitL = 1ull << L;
+  int cf = C - 1;
 #pragma unroll
-  for (int c = C - 1; c >= 0; --c) cidx = (b[c] == M) ? c : cidx;
-  T = C * L + __builtin_amdgcn_readlane(cidx, L);
+  for (int c = C - 2; c >= 0; --c) cf = (ballot(b[c] == M) & bitL) ? c : cf;
+  T = (M > kNegInf) ? C * L + cf : -1;
 }
 
 // Where one cube's results go.
@@ -132,7 +182,11 @@ struct Reporter {
     const bool mine = lane_id() == iw;
     snr_lane = mine ? s : snr_lane;
     toa_lane = mine ? T : toa_lane;
-    if (better(s, d, iw, best)) best = Best{s, d, iw, T};
+    const bool up = better(s, d, iw, best);
+    best.s = up ? s : best.s;
+    best.d = up ? d : best.d;
+    best.w = up ? iw : best.w;
+    best.t = up ? T : best.t;
   }
   __device__ __forceinline__ void flush() {
     const int l = lane_id();
@@ -219,12 +273,7 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
         float cur[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) cur[c] = 0.f;
-        for (int s = 0; s < n_sub; ++s) {
-          const int dl = cd.delays[d * n_sub + s];
-          const ST* row = zbase + s * rs + dl + C * l;
-#pragma unroll
-          for (int c = 0; c < C; ++c) cur[c] += to_f32(row[c]);
-        }
+        for (int s = 0; s < n_sub; ++s) add_row<C>(cur, zbase + s * rs, cd.delays[d * n_sub + s], l);
         nsfrb_chain<C>(pass, cur, rep);
       }
       rep.flush();

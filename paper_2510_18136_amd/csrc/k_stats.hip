@@ -354,24 +354,49 @@ __global__ __launch_bounds__(StatShape<V>::kWaves * kWave) void k_stats_norm(
   __shared__ uint32_t hist_all[kStatWaves][256];
   __shared__ double list_all[kStatWaves][64];
 
-  const int s = blockIdx.y;
-  const int p0 = blockIdx.x * kStatTilePix;
+  // Workgroups are dealt to the 8 XCDs round-robin; remap so that each XCD
+  // takes a contiguous run of (pixel tile, sub-band) items: neighbouring
+  // tiles share 128-byte lines of the [t][s][p] rows, which then stay in one
+  // L2 instead of being fetched once per XCD.
+  const unsigned n_items = gridDim.x * gridDim.y;
+  unsigned item = blockIdx.x + blockIdx.y * gridDim.x;
+  if ((n_items & 7u) == 0) item = (item & 7u) * (n_items >> 3) + (item >> 3);
+  const int s = (int)(item / gridDim.x);
+  const int p0 = (int)(item % gridDim.x) * kStatTilePix;
   const int w = threadIdx.x / kWave;
   const int l = lane_id();
   const size_t plane = (size_t)n_sub * n_pix;
 
   // this wave's pixel: p0 + w
   float xa[V];
-  // ---- load: coalesced rows of 16 pixels, transposed through LDS
+  // ---- load: rows of kStatTilePix pixels; every global load of the thread is
+  // issued first (one memory latency), then each chunk is transposed through LDS
+  constexpr int kPer = CT * kStatTilePix / (kStatWaves * kWave);   // values per thread per chunk
+  static_assert(kPer * kStatWaves * kWave == CT * kStatTilePix, "chunk must split evenly over the threads");
+  // thread i of a chunk reads pixel p0 + i % kStatTilePix of time row i / kStatTilePix;
+  // rows beyond n_t and pixels beyond n_pix load a valid address and become NaN
+  const int c_ld = threadIdx.x % kStatTilePix;
+  const bool pix_ok = p0 + c_ld < n_pix;
+  const InT* src = x + (size_t)s * n_pix + (pix_ok ? p0 + c_ld : 0);
+  constexpr int kRowStep = kStatWaves * kWave / kStatTilePix;      // time rows between q and q + 1
+  const int r0 = threadIdx.x / kStatTilePix;
+  float stage[V / VC][kPer];
 #pragma unroll
   for (int ch = 0; ch < V / VC; ++ch) {
-    const int t0 = ch * CT;
-    for (int i = threadIdx.x; i < CT * kStatTilePix; i += kStatWaves * kWave) {
-      const int rr = i / kStatTilePix, c = i % kStatTilePix;
-      const int t = t0 + rr, pp = p0 + c;
-      float v = __builtin_nanf("");
-      if (t < n_t && pp < n_pix) v = to_f32(x[(size_t)t * plane + (size_t)s * n_pix + pp]);
-      tile[rr * RS + c] = v;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = ch * CT + q * kRowStep + r0;
+      const bool ok = pix_ok && t < n_t;
+      const float v = to_f32(src[(size_t)(ok ? t : 0) * plane]);
+      stage[ch][q] = ok ? v : __builtin_nanf("");
+    }
+  }
+#pragma unroll
+  for (int ch = 0; ch < V / VC; ++ch) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = threadIdx.x + q * kStatWaves * kWave;
+      tile[(i / kStatTilePix) * RS + i % kStatTilePix] = stage[ch][q];
     }
     __syncthreads();
 #pragma unroll

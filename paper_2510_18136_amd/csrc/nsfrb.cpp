@@ -147,12 +147,26 @@ struct KernelClass {
 std::string single_kernel_name(const KernelClass& k);
 // Samples per lane: odd, so 64 lanes reading rows at a common delay hit
 // distinct LDS banks; 64*C > n_time, so every series ends in padding.
-static int samples_per_lane(int n_time) {
+// Samples per lane C: 64 C > n_time, so every series has a -inf padding sample.
+// FP32 rows are read one sample per register and C is odd: lanes C samples
+// apart hit distinct LDS banks. FP16 rows are read two samples per dword and C
+// is even with C/2 odd: every lane then starts on the same half of a dword (the
+// parity of the delay) and lanes C/2 dwords apart hit distinct banks.
+static int samples_per_lane(int n_time, int store) {
   int c = (n_time + 64) / 64;
-  if ((c & 1) == 0) c += 1;
+  if (store == NSFRB_F16) {
+    if (c & 1) c += 1;
+    if (((c / 2) & 1) == 0) c += 2;
+  } else if ((c & 1) == 0) {
+    c += 1;
+  }
   return c;
 }
-static int row_len(int C, int dmax_search) { return 64 * C + dmax_search + 1; }
+// Row length in samples: 64 C + the largest searched delay + 1 (whole dwords for FP16).
+static int row_len(int C, int dmax_search, int store) {
+  const int rs = 64 * C + dmax_search + 1;
+  return store == NSFRB_F16 ? (rs + 1) & ~1 : rs;
+}
 static size_t lds_bytes_for(int pix, int n_sub, int rs, int store) {
   return (size_t)pix * n_sub * rs * dtype_size(store);
 }
@@ -354,8 +368,8 @@ extern "C" int nsfrb_debug_plan_source(const nsfrb_search_config* cfg, char* out
   std::vector<int32_t> dl;
   compute_delays(*cfg, dl);
   const int dmax_search = max_delay_searchable(dl, cfg->n_dm, cfg->n_sub, cfg->n_time, nullptr);
-  const int C = samples_per_lane(cfg->n_time);
-  const int rs = row_len(C, dmax_search);
+  const int C = samples_per_lane(cfg->n_time, cfg->store_dtype);
+  const int rs = row_len(C, dmax_search, cfg->store_dtype);
   std::vector<int> pix = pix_candidates(cfg->n_dm, cfg->n_sub, rs, cfg->store_dtype);
   if (pix.empty()) {
     fail(NSFRB_ERR_UNSUPPORTED, "a pixel's rows do not fit in LDS");
@@ -452,8 +466,8 @@ extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfr
   h->device = cfg->device;
   compute_delays(h->cfg, h->delays);
   const int dmax_search = max_delay_searchable(h->delays, cfg->n_dm, cfg->n_sub, cfg->n_time, &h->dmaxv);
-  h->C = samples_per_lane(cfg->n_time);
-  h->rs = row_len(h->C, dmax_search);
+  h->C = samples_per_lane(cfg->n_time, cfg->store_dtype);
+  h->rs = row_len(h->C, dmax_search, cfg->store_dtype);
   std::vector<int> pix = pix_candidates(cfg->n_dm, cfg->n_sub, h->rs, cfg->store_dtype);
   if (pix.empty())
     return fail(NSFRB_ERR_UNSUPPORTED, "n_sub x (padded n_time + max delay) does not fit in LDS for this store dtype");
