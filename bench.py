@@ -9,6 +9,16 @@ at 5 sigma; 32 DM trials over 0-4000 pc/cm^3; widths 1, 2, 4, ..., 1024, 1200.
 A step is one whole search (noise statistics + normalisation, de-dispersion,
 boxcars, S/N, max/argmax maps, candidates) of the resident raw FP32 cube.
 Prints one JSON line: trials/s = pixels * DM trials * widths per second.
+
+Beside the headline, the same line carries (each can be switched off):
+  fp16_store  the same search with the normalised cube stored in FP16;
+  batch       64 uneven FP16 cubes (64^2-512^2 pixels, 8 or 16 sub-bands,
+              256-4096 samples, drawn log-uniformly with the total capped at
+              128 GB; 8 DMs 0-1000, widths 1-16; noise plus one injected
+              pulse each, generated on the device, already normalised) in one
+              persistent graph-captured launch, against one launch per cube;
+  classifier  BF16-MFMA training steps (batch 64 cutouts of 64 x 32 x 32 x 16)
+              and inference, against the dense BF16 matrix-core peak.
 """
 import argparse
 import hashlib
@@ -23,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0      # dense BF16 matrix cores (no sparsity)
 # FP32 vector issue rate without packed math or FMA: 256 CU * 64 lanes * 2.4 GHz
 PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 
@@ -91,6 +102,110 @@ def cpu_baseline(cube, meta, target_s=12.0):
                       f"12 widths), {elapsed:.2f} s of NumPy FP64 on one thread"}
 
 
+def batch_shapes(seed=4, n=64, cap_bytes=128e9):
+    """Cube shapes of the batched workload: side log-uniform 64-512, samples
+    log-uniform 256-4096, sub-bands 8 or 16; redrawn with seed + 1 until the
+    FP16 total fits the cap."""
+    while True:
+        rng = np.random.default_rng(seed)
+        side = np.rint(np.exp(rng.uniform(np.log(64), np.log(512), n))).astype(int)
+        nt = np.rint(np.exp(rng.uniform(np.log(256), np.log(4096), n))).astype(int)
+        ns = rng.choice([8, 16], n)
+        total = float(np.sum(side * side * ns * nt * 2))
+        if total <= cap_bytes:
+            return [(int(a), int(b), int(c)) for a, b, c in zip(side, ns, nt)], total, seed
+        seed += 1
+
+
+def bench_batch(torch, nsfrb, reps=3):
+    shapes, total, seed = batch_shapes()
+    dms, widths = np.linspace(0.0, 1000.0, 8), [1, 2, 4, 8, 16]
+    t0 = time.time()
+    cfgs, bufs = [], []
+    for side, ns, nt in shapes:
+        cfgs.append(nsfrb.SearchConfig(side, side, nt, np.linspace(1.311, 1.499, ns), dms, widths,
+                                       in_dtype="f16", store_dtype="f16", norm="none", layout="pst",
+                                       snr_threshold=6.0))
+        bufs.append(torch.empty(side * side * ns * nt, dtype=torch.float16, device="cuda"))
+    ptrs = [b.data_ptr() for b in bufs]
+    for k, ((side, ns, nt), cfg) in enumerate(zip(shapes, cfgs)):
+        nsfrb.generate_noise(ptrs[k], "f16", "pst", side * side, ns, nt, 1000 + k)
+        off = nsfrb.SearchConfig(side, side, nt, cfg.freqs, [500.0], widths).delays()
+        nsfrb.inject_boxcars([ptrs[k]], "f16", "pst", side * side, ns, nt,
+                             [(0, (side // 2) * side + side // 2, min(20, nt - 8), 4, 1.0)], off)
+    torch.cuda.synchronize()
+    t_gen = time.time() - t0
+    t0 = time.time()
+    b = nsfrb.Batch(cfgs)
+    t_plan = time.time() - t0
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn(ptrs, stream.cuda_stream)                  # warm-up (captures the graph on first use)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(reps):
+            fn(ptrs, stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return max(e0.elapsed_time(e1), (time.perf_counter() - w0) * 1e3) / reps
+
+    ms_graph = timed(b.run)
+    info = b.info()
+    ms_sep = timed(b.run_separate)
+    b.close()
+    n_pix = sum(sd * sd for sd, _, _ in shapes)
+    trials = n_pix * len(dms) * len(widths)
+    by = total + n_pix * (len(dms) * len(widths) * 8 + 16)
+    del bufs
+    torch.cuda.empty_cache()
+    return {"workload": f"64 uneven FP16 cubes (shape seed {seed}), {total / 1e9:.1f} GB in total, "
+                        f"{n_pix} pixels; 8 DMs 0-1000, widths 1-16",
+            "ms_per_run": ms_graph, "trials_per_s": trials / (ms_graph * 1e-3),
+            "separate_launches_ms": ms_sep, "speedup_vs_separate": ms_sep / ms_graph,
+            "algorithmic_GBs": by / (ms_graph * 1e-3) / 1e9, "hbm_frac": by / (ms_graph * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "graph_replayed": info["graph"], "kernel_classes": info["classes"], "work_items": info["work_items"],
+            "plan_seconds": t_plan, "generate_seconds": t_gen}
+
+
+def bench_classifier(torch, nsfrb, steps=20, warmup=3, batch=64):
+    T, Y, X, S = 64, 32, 32, 16
+    P = T * Y * X
+    fwd = sum(2 * P * 32 * 27 * cin for cin in (16, 32, 32, 32))            # four convolutions
+    train = 2 * fwd + sum(2 * P * 32 * 27 * cin for cin in (32, 32, 32))   # + weight grads + data grads (layers 2-4)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    x = torch.randn((batch, T, Y, X, S), device="cuda", generator=g).to(torch.bfloat16).view(torch.int16)
+    y = (torch.rand(batch, device="cuda", generator=g) < 0.5).float()
+    prob = torch.empty(batch, device="cuda")
+    stream = torch.cuda.current_stream()
+    with nsfrb.Classifier(max_batch=batch, n_time=T, ny=Y) as c:
+        def run(fn, n):
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(n):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / n
+        ms_train = run(lambda: c.train_step(x.data_ptr(), y.data_ptr(), batch, update=True,
+                                            stream=stream.cuda_stream, want_loss=False), steps)
+        ms_inf = run(lambda: c.infer(x.data_ptr(), batch, prob.data_ptr(), stream=stream.cuda_stream), steps)
+    tf_train = train * batch / (ms_train * 1e-3) / 1e12
+    tf_inf = fwd * batch / (ms_inf * 1e-3) / 1e12
+    return {"workload": f"batch {batch} cutouts of {T} x {Y} x {X} x {S}, 4 conv layers of 32 channels",
+            "train_ms_per_step": ms_train, "train_cutouts_per_s": batch / (ms_train * 1e-3),
+            "train_TFLOPs": tf_train, "infer_ms_per_batch": ms_inf, "infer_cutouts_per_s": batch / (ms_inf * 1e-3),
+            "infer_TFLOPs": tf_inf, "roofline": {"bound": "mfma", "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                                                 "train_frac": tf_train / PEAK_BF16_TFLOPS,
+                                                 "infer_frac": tf_inf / PEAK_BF16_TFLOPS,
+                                                 "algorithmic_flop_per_cutout": {"train": train, "infer": fwd}}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +213,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-classifier", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the search is built and "
@@ -188,6 +305,15 @@ def main():
               flush=True)
     del x
     torch.cuda.empty_cache()
+    if not args.no_batch:
+        print("[bench] batched form: generating 64 uneven cubes on the device", file=sys.stderr, flush=True)
+        out["batch"] = bench_batch(torch, nsfrb)
+        print(f"[bench] batch {out['batch']['ms_per_run']:.2f} ms (separate {out['batch']['separate_launches_ms']:.2f})",
+              file=sys.stderr, flush=True)
+    if not args.no_classifier:
+        out["classifier"] = bench_classifier(torch, nsfrb)
+        print(f"[bench] classifier train {out['classifier']['train_ms_per_step']:.2f} ms/step "
+              f"({out['classifier']['train_TFLOPs']:.1f} TFLOP/s)", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a pixel sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cube, meta)

@@ -174,10 +174,12 @@ nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* info);
  * section 2.2 batches search tasks per timescale). All configurations must
  * share the DM trials, widths, store dtype, normalisation, layout, input
  * dtype and device; nx, ny, n_sub, n_time and frequencies may differ.
- * nsfrb_batch_run enqueues the statistics of every cube, then ONE persistent
- * search launch whose workgroups stride over the work items of all cubes,
- * then the candidates of every cube. The sequence is captured once as a
- * hipGraph and replayed while the cube pointers stay the same.
+ * nsfrb_batch_run enqueues the statistics of every cube, then one persistent
+ * search launch per kernel class (cubes whose tuned plans share the samples per
+ * lane and pixels per workgroup; each launch's workgroups stride over the work
+ * items of its cubes, with a grid sized to that kernel's occupancy), then the
+ * candidates of every cube. The sequence is captured once as a hipGraph and
+ * replayed while the cube pointers stay the same.
  * Results are bitwise equal to nsfrb_batch_run_separate, which runs the same
  * kernel body with one plain launch per cube. */
 typedef struct nsfrb_batch nsfrb_batch;
@@ -198,7 +200,7 @@ nsfrb_status nsfrb_batch_maps_get(nsfrb_batch* b, int32_t cube, float* snr_max, 
 nsfrb_status nsfrb_batch_best_get(nsfrb_batch* b, int32_t cube, float* snr, int32_t* dm_index, int32_t* width_index,
                                   int32_t* toa);
 nsfrb_status nsfrb_batch_zcube_device(nsfrb_batch* b, int32_t cube, const void** d_z);
-/* info[0] work items, [1] persistent grid size, [2] LDS bytes, [3] kernel
+/* info[0] work items, [1] workgroups over all class launches, [2] largest LDS bytes, [3] kernel
  * classes, [4] 1 if the last run replayed a captured graph. */
 nsfrb_status nsfrb_batch_info_get(nsfrb_batch* b, int64_t* info);
 

@@ -256,23 +256,28 @@ static std::string gen_source(int store, int nw, int npass, const std::string& c
   for (const auto& k : single)
     o << "extern \"C\" __global__ __launch_bounds__(512) void " << single_kernel_name(k)
       << "(nsfrb::CubeDesc cd) { search_cube<" << k.C << ", " << k.PIX << ">(cd); }\n";
-  if (!batch.empty()) {
-    o << "extern \"C\" __global__ __launch_bounds__(512) void nsfrb_batch_kernel("
-         "const nsfrb::CubeDesc* __restrict__ descs, int n_cubes, long long n_items) {\n"
+  // one persistent kernel per class of the batch: its workgroups take the work
+  // items of that class's cubes (descriptors contiguous, item_begin relative)
+  // from a device counter, one item at a time, until the counter passes n_items
+  for (size_t i = 0; i < batch.size(); ++i)
+    o << "extern \"C\" __global__ __launch_bounds__(512) void nsfrb_batch_kernel_" << i
+      << "(const nsfrb::CubeDesc* __restrict__ descs, int n_cubes, long long n_items,"
+         " unsigned long long* __restrict__ next_item) {\n"
          "  using namespace nsfrb;\n"
          "  extern __shared__ unsigned char lds_raw[];\n"
          "  __shared__ Best red[kWaves];\n"
+         "  __shared__ long long item;\n"
          "  ST* zl = reinterpret_cast<ST*>(lds_raw);\n"
-         "  for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {\n"
-         "    const int ci = find_cube(descs, n_cubes, it);\n"
-         "    const CubeDesc cd = descs[ci];\n"
-         "    const int local = (int)(it - cd.item_begin);\n"
-         "    switch (cd.cls) {\n";
-    for (size_t i = 0; i < batch.size(); ++i)
-      o << "      case " << i << ": search_group<" << batch[i].C << ", " << batch[i].PIX << ">(cd, local * "
-        << batch[i].PIX << ", zl, red); break;\n";
-    o << "      default: break;\n    }\n  }\n}\n";
-  }
+         "  for (;;) {\n"
+         "    if (threadIdx.x == 0) item = (long long)atomicAdd(next_item, 1ull);\n"
+         "    __syncthreads();\n"
+         "    const long long it = item;\n"
+         "    __syncthreads();\n"
+         "    if (it >= n_items) break;\n"
+         "    const CubeDesc cd = descs[find_cube(descs, n_cubes, it)];\n"
+         "    search_group<" << batch[i].C << ", " << batch[i].PIX << ">(cd, (int)(it - cd.item_begin) * "
+      << batch[i].PIX << ", zl, red);\n"
+         "  }\n}\n";
   return o.str();
 }
 
@@ -818,17 +823,26 @@ extern "C" nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* i
 }
 
 // ------------------------------------------------------------------- batch
+// One kernel class of a batch: the cubes whose tuned plan has this (C, PIX).
+struct BatchClass {
+  KernelClass k;
+  hipFunction_t fn = nullptr;
+  int first_desc = 0, n_cubes = 0;       // descriptors [first_desc, first_desc + n_cubes)
+  long long n_items = 0;
+  size_t lds = 0;
+  unsigned grid = 0;
+};
+
 struct nsfrb_batch {
   std::vector<nsfrb_search*> cubes;
   int device = 0, store = 0, nw = 0;
-  std::vector<KernelClass> classes;
-  std::vector<CubeDescHost> descs;        // item_begin / cls filled, z set per run
+  std::vector<BatchClass> classes;
+  std::vector<CubeDescHost> descs;        // grouped by class; item_begin relative to the class
+  std::vector<int> desc_of_cube;          // cube index -> descriptor index
   CubeDescHost* d_descs = nullptr;
+  unsigned long long* d_next = nullptr;   // per-class work counters, cleared by a fill kernel each run
   long long n_items = 0;
-  unsigned grid = 0;
-  size_t lds = 0;
   hipModule_t mod = nullptr;
-  hipFunction_t fn = nullptr;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -844,6 +858,7 @@ static void batch_release(nsfrb_batch* b) {
   if (b->graph) hipGraphDestroy(b->graph);
   if (b->cap_stream) hipStreamDestroy(b->cap_stream);
   if (b->d_descs) hipFree(b->d_descs);
+  if (b->d_next) hipFree(b->d_next);
   if (b->done) hipEventDestroy(b->done);
   for (auto* h : b->cubes) release(h);
   delete b;
@@ -876,34 +891,59 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
     b->cubes.push_back(h);
   }
   // kernel classes: distinct (samples per lane, pixels per workgroup) of the cubes' tuned plans
-  long long items = 0;
-  for (auto* h : b->cubes) {
+  std::vector<int> cls_of(b->cubes.size());
+  for (size_t i = 0; i < b->cubes.size(); ++i) {
+    nsfrb_search* h = b->cubes[i];
     int cls = -1;
     for (size_t k = 0; k < b->classes.size(); ++k)
-      if (b->classes[k].C == h->C && b->classes[k].PIX == h->pix) cls = (int)k;
-    if (cls < 0) { cls = (int)b->classes.size(); b->classes.push_back({h->C, h->pix}); }
-    CubeDescHost d = cube_desc(h, nullptr, h->n_pix);
-    d.cls = cls;
-    d.item_begin = items;
-    items += (h->n_pix + h->pix - 1) / h->pix;
-    b->descs.push_back(d);
-    b->lds = std::max(b->lds, lds_bytes_for(h->pix, h->cfg.n_sub, h->rs, h->cfg.store_dtype));
+      if (b->classes[k].k.C == h->C && b->classes[k].k.PIX == h->pix) cls = (int)k;
+    if (cls < 0) {
+      cls = (int)b->classes.size();
+      b->classes.emplace_back();
+      b->classes.back().k = {h->C, h->pix};
+    }
+    cls_of[i] = cls;
   }
-  b->n_items = items;
+  b->desc_of_cube.assign(b->cubes.size(), -1);
+  for (size_t c = 0; c < b->classes.size(); ++c) {
+    BatchClass& bc = b->classes[c];
+    bc.first_desc = (int)b->descs.size();
+    for (size_t i = 0; i < b->cubes.size(); ++i) {
+      if (cls_of[i] != (int)c) continue;
+      nsfrb_search* h = b->cubes[i];
+      CubeDescHost d = cube_desc(h, nullptr, h->n_pix);
+      d.cls = (int)c;
+      d.item_begin = bc.n_items;
+      bc.n_items += (h->n_pix + h->pix - 1) / h->pix;
+      b->desc_of_cube[i] = (int)b->descs.size();
+      b->descs.push_back(d);
+      bc.lds = std::max(bc.lds, lds_bytes_for(h->pix, h->cfg.n_sub, h->rs, h->cfg.store_dtype));
+    }
+    bc.n_cubes = (int)b->descs.size() - bc.first_desc;
+    b->n_items += bc.n_items;
+  }
   std::string chain;
   int npass = 1;
   nsfrb_status st = gen_chain(b->cubes[0]->widths, chain, &npass);
   if (st != NSFRB_OK) return st;
   HIP_TRY(hipSetDevice(b->device));
-  st = load_module(b->device, gen_source(b->store, b->nw, npass, chain, {}, b->classes), &b->mod);
+  std::vector<KernelClass> ks;
+  for (const auto& bc : b->classes) ks.push_back(bc.k);
+  st = load_module(b->device, gen_source(b->store, b->nw, npass, chain, {}, ks), &b->mod);
   if (st != NSFRB_OK) return st;
-  HIP_TRY(hipModuleGetFunction(&b->fn, b->mod, "nsfrb_batch_kernel"));
   int n_cu = 0;
   HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, b->device));
-  const int per_cu = std::max(1, (int)(kLdsBudget / std::max<size_t>(b->lds, 1)));
-  const long long g = (long long)n_cu * std::min(per_cu, 2);
-  b->grid = (unsigned)std::max(1LL, std::min(g, b->n_items));
+  for (size_t c = 0; c < b->classes.size(); ++c) {
+    BatchClass& bc = b->classes[c];
+    HIP_TRY(hipModuleGetFunction(&bc.fn, b->mod, ("nsfrb_batch_kernel_" + std::to_string(c)).c_str()));
+    // a persistent grid of as many workgroups as this class's kernel keeps resident
+    int per_cu = 0;
+    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bc.fn, kSearchThreads, bc.lds));
+    const long long g = (long long)n_cu * std::max(1, per_cu);
+    bc.grid = (unsigned)std::max(1LL, std::min(g, bc.n_items));
+  }
   HIP_TRY(dalloc(&b->d_descs, b->descs.size()));
+  HIP_TRY(dalloc(&b->d_next, b->classes.size()));
   HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
   *out = b.release();
@@ -961,12 +1001,16 @@ static nsfrb_status batch_candidates(nsfrb_batch* b, hipStream_t st) {
 static nsfrb_status batch_enqueue(nsfrb_batch* b, const void* const* d_cubes, hipStream_t st) {
   nsfrb_status s = batch_stats(b, d_cubes, st);
   if (s != NSFRB_OK) return s;
-  void* args[] = {(void*)&b->d_descs, nullptr, nullptr};
-  int n = (int)b->cubes.size();
-  long long items = b->n_items;
-  args[1] = &n;
-  args[2] = &items;
-  HIP_TRY(hipModuleLaunchKernel(b->fn, b->grid, 1, 1, kSearchThreads, 1, 1, (unsigned)b->lds, st, args, nullptr));
+  for (size_t c = 0; c < b->classes.size(); ++c) {
+    const BatchClass& bc = b->classes[c];
+    const CubeDescHost* descs = b->d_descs + bc.first_desc;
+    int n = bc.n_cubes;
+    long long items = bc.n_items;
+    unsigned long long* next = b->d_next + c;
+    HIP_TRY(launch_zero_u64(next, st));
+    void* args[] = {(void*)&descs, &n, &items, (void*)&next};
+    HIP_TRY(hipModuleLaunchKernel(bc.fn, bc.grid, 1, 1, kSearchThreads, 1, 1, (unsigned)bc.lds, st, args, nullptr));
+  }
   return batch_candidates(b, st);
 }
 
@@ -984,7 +1028,7 @@ extern "C" nsfrb_status nsfrb_batch_run(nsfrb_batch* b, const void* const* d_cub
     if (b->ran) HIP_TRY(hipEventSynchronize(b->done));
     for (size_t i = 0; i < b->cubes.size(); ++i) {
       nsfrb_search* h = b->cubes[i];
-      b->descs[i].z = h->cfg.layout == NSFRB_LAYOUT_TSP ? h->d_z : d_cubes[i];
+      b->descs[b->desc_of_cube[i]].z = h->cfg.layout == NSFRB_LAYOUT_TSP ? h->d_z : d_cubes[i];
     }
     HIP_TRY(hipMemcpy(b->d_descs, b->descs.data(), b->descs.size() * sizeof(CubeDescHost), hipMemcpyHostToDevice));
   }
@@ -1083,9 +1127,14 @@ extern "C" nsfrb_status nsfrb_batch_zcube_device(nsfrb_batch* b, int32_t cube, c
 extern "C" nsfrb_status nsfrb_batch_info_get(nsfrb_batch* b, int64_t* info) {
   g_last_error.clear();
   if (!b || !info) return fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  int64_t grid = 0, lds = 0;
+  for (const auto& bc : b->classes) {
+    grid += bc.grid;
+    lds = std::max<int64_t>(lds, (int64_t)bc.lds);
+  }
   info[0] = b->n_items;
-  info[1] = b->grid;
-  info[2] = (int64_t)b->lds;
+  info[1] = grid;
+  info[2] = lds;
   info[3] = (int64_t)b->classes.size();
   info[4] = b->last_graph ? 1 : 0;
   return NSFRB_OK;
