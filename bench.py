@@ -117,7 +117,7 @@ def batch_shapes(seed=4, n=64, cap_bytes=128e9):
         seed += 1
 
 
-def bench_batch(torch, nsfrb, reps=3):
+def bench_batch(nsfrb, hip, reps=3):
     shapes, total, seed = batch_shapes()
     dms, widths = np.linspace(0.0, 1000.0, 8), [1, 2, 4, 8, 16]
     t0 = time.time()
@@ -126,41 +126,41 @@ def bench_batch(torch, nsfrb, reps=3):
         cfgs.append(nsfrb.SearchConfig(side, side, nt, np.linspace(1.311, 1.499, ns), dms, widths,
                                        in_dtype="f16", store_dtype="f16", norm="none", layout="pst",
                                        snr_threshold=6.0))
-        bufs.append(torch.empty(side * side * ns * nt, dtype=torch.float16, device="cuda"))
-    ptrs = [b.data_ptr() for b in bufs]
+        bufs.append(hip.Buffer(side * side * ns * nt * 2))
+    ptrs = [b.ptr for b in bufs]
     for k, ((side, ns, nt), cfg) in enumerate(zip(shapes, cfgs)):
         nsfrb.generate_noise(ptrs[k], "f16", "pst", side * side, ns, nt, 1000 + k)
         off = nsfrb.SearchConfig(side, side, nt, cfg.freqs, [500.0], widths).delays()
         nsfrb.inject_boxcars([ptrs[k]], "f16", "pst", side * side, ns, nt,
                              [(0, (side // 2) * side + side // 2, min(20, nt - 8), 4, 1.0)], off)
-    torch.cuda.synchronize()
+    hip.synchronize()
     t_gen = time.time() - t0
     t0 = time.time()
     b = nsfrb.Batch(cfgs)
     t_plan = time.time() - t0
-    stream = torch.cuda.current_stream()
 
     def timed(fn):
-        fn(ptrs, stream.cuda_stream)                  # warm-up (captures the graph on first use)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn(ptrs, 0)                                    # warm-up (captures the graph on first use)
+        hip.synchronize()
+        tm = hip.Timer()
         w0 = time.perf_counter()
-        e0.record(stream)
+        tm.start()
         for _ in range(reps):
-            fn(ptrs, stream.cuda_stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return max(e0.elapsed_time(e1), (time.perf_counter() - w0) * 1e3) / reps
+            fn(ptrs, 0)
+        ms = tm.stop()
+        hip.synchronize()
+        tm.close()
+        return max(ms, (time.perf_counter() - w0) * 1e3) / reps
 
     ms_graph = timed(b.run)
     info = b.info()
     ms_sep = timed(b.run_separate)
     b.close()
+    for x in bufs:
+        x.close()
     n_pix = sum(sd * sd for sd, _, _ in shapes)
     trials = n_pix * len(dms) * len(widths)
     by = total + n_pix * (len(dms) * len(widths) * 8 + 16)
-    del bufs
-    torch.cuda.empty_cache()
     return {"workload": f"64 uneven FP16 cubes (shape seed {seed}), {total / 1e9:.1f} GB in total, "
                         f"{n_pix} pixels; 8 DMs 0-1000, widths 1-16",
             "ms_per_run": ms_graph, "trials_per_s": trials / (ms_graph * 1e-3),
@@ -170,31 +170,31 @@ def bench_batch(torch, nsfrb, reps=3):
             "plan_seconds": t_plan, "generate_seconds": t_gen}
 
 
-def bench_classifier(torch, nsfrb, steps=20, warmup=3, batch=64):
+def bench_classifier(nsfrb, hip, steps=20, warmup=3, batch=64):
     T, Y, X, S = 64, 32, 32, 16
     P = T * Y * X
     fwd = sum(2 * P * 32 * 27 * cin for cin in (16, 32, 32, 32))            # four convolutions
     train = 2 * fwd + sum(2 * P * 32 * 27 * cin for cin in (32, 32, 32))   # + weight grads + data grads (layers 2-4)
-    g = torch.Generator(device="cuda").manual_seed(7)
-    x = torch.randn((batch, T, Y, X, S), device="cuda", generator=g).to(torch.bfloat16).view(torch.int16)
-    y = (torch.rand(batch, device="cuda", generator=g) < 0.5).float()
-    prob = torch.empty(batch, device="cuda")
-    stream = torch.cuda.current_stream()
+    x = hip.Buffer(batch * P * S * 2)
+    nsfrb.generate_noise(x.ptr, "bf16", "pst", batch, 1, P * S, 7)           # N(0,1) BF16 cutouts
+    y = hip.Buffer(batch * 4).upload((np.arange(batch) % 2).astype(np.float32))
+    prob = hip.Buffer(batch * 4)
     with nsfrb.Classifier(max_batch=batch, n_time=T, ny=Y) as c:
         def run(fn, n):
             for _ in range(warmup):
                 fn()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
+            hip.synchronize()
+            tm = hip.Timer()
+            tm.start()
             for _ in range(n):
                 fn()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / n
-        ms_train = run(lambda: c.train_step(x.data_ptr(), y.data_ptr(), batch, update=True,
-                                            stream=stream.cuda_stream, want_loss=False), steps)
-        ms_inf = run(lambda: c.infer(x.data_ptr(), batch, prob.data_ptr(), stream=stream.cuda_stream), steps)
+            ms = tm.stop() / n
+            tm.close()
+            return ms
+        ms_train = run(lambda: c.train_step(x.ptr, y.ptr, batch, update=True, stream=0, want_loss=False), steps)
+        ms_inf = run(lambda: c.infer(x.ptr, batch, prob.ptr, stream=0), steps)
+    for b in (x, y, prob):
+        b.close()
     tf_train = train * batch / (ms_train * 1e-3) / 1e12
     tf_inf = fwd * batch / (ms_inf * 1e-3) / 1e12
     return {"workload": f"batch {batch} cutouts of {T} x {Y} x {X} x {S}, 4 conv layers of 32 channels",
@@ -221,8 +221,10 @@ def main():
               f"measured on a single MI355X).", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_2510_18136_amd import nsfrb, synth
+    # device memory, copies and events through the library's own HIP runtime (no
+    # torch in this process: a torch wheel's bundled runtime keeps fewer of the
+    # search's workgroups resident per CU)
+    from paper_2510_18136_amd import hip, nsfrb, synth
 
     if not os.path.exists(nsfrb.LIB_PATH):
         from paper_2510_18136_amd import build
@@ -231,10 +233,9 @@ def main():
     t0 = time.time()
     cube, meta = synth.config2(seed=2)
     print(f"[bench] generated survey cube {cube.shape} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    dev = torch.device("cuda:0")
-    x = torch.from_numpy(cube).to(dev)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
+    xbuf = hip.Buffer(cube.nbytes).upload(cube)
+    hip.synchronize()
+    x_ptr = xbuf.ptr
 
     def make(store):
         cfg = nsfrb.SearchConfig(meta["nx"], meta["ny"], cube.shape[0], meta["freqs"], meta["dms"],
@@ -243,23 +244,23 @@ def main():
 
     def timed(search, steps, warmup):
         for _ in range(warmup):
-            search.run(x.data_ptr(), stream.cuda_stream)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            search.run(x_ptr, 0)
+        hip.synchronize()
+        tm = hip.Timer()
         w0 = time.perf_counter()
-        e0.record(stream)
+        tm.start()
         for _ in range(steps):
-            search.run(x.data_ptr(), stream.cuda_stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
+            search.run(x_ptr, 0)
+        ev = tm.stop() / steps
+        hip.synchronize()
         wall = (time.perf_counter() - w0) * 1e3 / steps
-        ev = e0.elapsed_time(e1) / steps
+        tm.close()
         # per-stage device times (HIP events on the run's stream), averaged over a few runs
         search.profiling(True)
         st = np.zeros(3)
         nrep = max(3, min(steps, 10))
         for _ in range(nrep):
-            search.run(x.data_ptr(), stream.cuda_stream)
+            search.run(x_ptr, 0)
             st += search.stage_times_ms()
         search.profiling(False)
         return max(wall, ev), st / nrep
@@ -292,26 +293,27 @@ def main():
                                   "100 pulses, 20 zero-DM spikes, 2 stripes (seed 2)",
                       "pixels": n_pix, "sub_bands": 16, "samples": 2048, "dm_trials": n_dm, "widths": n_w},
            "stage_ms": {"stats_norm": stages[0], "search": stages[1], "candidates": stages[2]},
-           "roofline": roof, "hbm": hbm, "candidates_found": ntot}
+           "roofline": roof, "hbm": hbm, "candidates_found": ntot, "search_plan": s32.plan_info()}
     s32.close()
     if not args.no_fp16:
         cfg16, s16 = make("f16")
         ms16, st16 = timed(s16, args.steps, args.warmup)
+        plan16 = s16.plan_info()
         s16.close()
         out["fp16_store"] = {"ms_per_step": ms16, "value": trials / (ms16 * 1e-3),
                              "stage_ms": {"stats_norm": st16[0], "search": st16[1], "candidates": st16[2]},
-                             "speedup_vs_fp32": ms / ms16, "search_speedup_vs_fp32": stages[1] / st16[1]}
-        print(f"[bench] fp16 {ms16:.3f} ms/step, stages {st16.round(3).tolist()} ms", file=sys.stderr,
-              flush=True)
-    del x
-    torch.cuda.empty_cache()
+                             "speedup_vs_fp32": ms / ms16, "search_speedup_vs_fp32": stages[1] / st16[1],
+                             "search_plan": plan16}
+        print(f"[bench] fp16 {ms16:.3f} ms/step, stages {st16.round(3).tolist()} ms, plan {plan16}",
+              file=sys.stderr, flush=True)
+    xbuf.close()
     if not args.no_batch:
         print("[bench] batched form: generating 64 uneven cubes on the device", file=sys.stderr, flush=True)
-        out["batch"] = bench_batch(torch, nsfrb)
+        out["batch"] = bench_batch(nsfrb, hip)
         print(f"[bench] batch {out['batch']['ms_per_run']:.2f} ms (separate {out['batch']['separate_launches_ms']:.2f})",
               file=sys.stderr, flush=True)
     if not args.no_classifier:
-        out["classifier"] = bench_classifier(torch, nsfrb)
+        out["classifier"] = bench_classifier(nsfrb, hip)
         print(f"[bench] classifier train {out['classifier']['train_ms_per_step']:.2f} ms/step "
               f"({out['classifier']['train_TFLOPs']:.1f} TFLOP/s)", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:

@@ -165,8 +165,9 @@ nsfrb_status nsfrb_profiling_enable(nsfrb_search* h, int32_t on);
 nsfrb_status nsfrb_stage_times_get(nsfrb_search* h, float* ms3);
 
 /* Plan of the search kernel: info[0] samples per lane, info[1] pixels per
- * workgroup (chosen by the autotuner), info[2] LDS row length, info[3] LDS
- * bytes per workgroup. */
+ * workgroup, info[2] LDS row length, info[3] LDS bytes per workgroup, info[4]
+ * threads per workgroup (pixels and threads per workgroup chosen by the
+ * autotuner); host_out holds 5 values. */
 nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* info);
 
 /* ------------------------------------------------------------------ batch

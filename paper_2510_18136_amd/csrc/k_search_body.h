@@ -12,12 +12,12 @@
 // n_sub and n_t stay runtime values.
 //
 // Layout and work split (gfx950, wave64):
-//  * a workgroup of kWaves waves takes PIX pixels at a time; their normalised
+//  * a workgroup of NW waves (8 or 16) takes PIX pixels at a time; their normalised
 //    series z[s][0..n_t) are staged in LDS, one row per sub-band of rs
 //    samples; samples at and beyond n_t hold -inf, so any window that reaches
 //    past the end of a de-dispersed series sums to -inf and is never a maximum;
-//  * kWaves/PIX waves share a pixel and split its DM trials round-robin (the
-//    "DM chunk" of a wave is every (kWaves/PIX)-th trial);
+//  * NW/PIX waves share a pixel and split its DM trials round-robin (the
+//    "DM chunk" of a wave is every (NW/PIX)-th trial);
 //  * lane l holds the C consecutive samples t = C*l + c (FP32 rows: C odd, so
 //    lanes hit distinct LDS banks at any delay; FP16 rows: C even with C/2
 //    odd, read as dwords holding two samples);
@@ -37,7 +37,6 @@
 
 namespace nsfrb {
 
-constexpr int kWaves = 8;
 constexpr float kNegInf = -__builtin_inff();
 
 // Value of x held by lane l+1 (lane 63 reads 0). Only used where the sum it
@@ -169,32 +168,41 @@ struct CubeOut {
   int n_pix;
 };
 
-// Per-DM results are kept in lane iw of two registers and stored together
-// (lanes 0..NSFRB_NW-1 write [d][iw][p]) by flush().
+// Per-DM results: the raw maximum of width iw and its TOA are kept in lane iw
+// of two registers. flush() turns all of them into S/N at once (lane iw
+// divides by its own normaliser), stores them ([d][iw][p], lanes
+// 0..NSFRB_NW-1), and folds the DM's best width into the running best.
 struct Reporter {
   CubeOut o;
   int p, d;
   Best best;
   float snr_lane;
   int toa_lane;
+  float norm_lane;          // lane iw: sqrt(n_sub * width[iw])
   __device__ __forceinline__ void emit(int iw, float M, int T) {
-    const float s = (M > kNegInf) ? M / o.norms[iw] : kNegInf;
     const bool mine = lane_id() == iw;
-    snr_lane = mine ? s : snr_lane;
+    snr_lane = mine ? M : snr_lane;
     toa_lane = mine ? T : toa_lane;
-    const bool up = better(s, d, iw, best);
-    best.s = up ? s : best.s;
-    best.d = up ? d : best.d;
-    best.w = up ? iw : best.w;
-    best.t = up ? T : best.t;
   }
   __device__ __forceinline__ void flush() {
     const int l = lane_id();
-    if (l < NSFRB_NW) {
+    const bool act = l < NSFRB_NW;
+    const float s = (act && snr_lane > kNegInf) ? snr_lane / norm_lane : kNegInf;
+    if (act) {
       const size_t idx = ((size_t)d * NSFRB_NW + l) * o.n_pix + p;
-      o.snr_max[idx] = snr_lane;
+      o.snr_max[idx] = s;
       o.toa[idx] = toa_lane;
     }
+    // the DM's best width: the largest S/N, the smallest width index on ties
+    // (with every width at -inf, width 0 at -inf never beats the running best)
+    const float smax = wave_max_f(s);
+    const int w = __ffsll((long long)ballot(act && s == smax)) - 1;
+    const int t = __builtin_amdgcn_readlane(toa_lane, w);
+    const bool up = better(smax, d, w, best);
+    best.s = up ? smax : best.s;
+    best.d = up ? d : best.d;
+    best.w = up ? w : best.w;
+    best.t = up ? t : best.t;
   }
   template <int C>
   __device__ __forceinline__ void operator()(int iw, const float (&b)[C]) {
@@ -234,11 +242,14 @@ __device__ void nsfrb_chain(int pass, float (&cur)[C], R& rep);
 namespace nsfrb {
 
 // One work item: PIX consecutive pixels starting at p0 of one cube.
-// Requires all kWaves waves of the workgroup (it contains barriers).
-template <int C, int PIX>
+// Requires all NW waves of the workgroup (it contains barriers).
+template <int C, int PIX, int NW>
 __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl, Best* red) {
-  constexpr int WPP = kWaves / PIX;        // waves per pixel
-  const int wv = threadIdx.x / kWave;
+  static_assert(NW % PIX == 0, "every pixel of a group gets the same number of waves");
+  constexpr int WPP = NW / PIX;            // waves per pixel
+  // the wave index is uniform across the wave; saying so lets every per-DM
+  // value (delays, DM bounds) come through the scalar cache
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int l = lane_id();
   const int slot = wv / WPP;               // which pixel of the group
   const int wq = wv % WPP;                 // this wave's DM chunk: d = wq, wq + WPP, ...
@@ -259,12 +270,23 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
   }
   __syncthreads();
   const int p = p0 + slot;
-  Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, p, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0};
+  Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, p, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0,
+               l < NSFRB_NW ? cd.norms[l] : 1.f};
   if (p < cd.n_pix) {
     const ST* zbase = zl + (size_t)slot * n_sub * rs;
-    for (int d = wq; d < cd.n_dm; d += WPP) {
+    // a DM's delays sit in lanes 0..n_sub-1 of one register (one coalesced
+    // load, issued a DM ahead); the sub-band loop reads them with v_readlane
+    const int n_dm = cd.n_dm;
+    int dl_next = (wq < n_dm && l < n_sub) ? cd.delays[wq * n_sub + l] : 0;
+    int dmax_next = wq < n_dm ? cd.dmax[wq] : 0;
+    for (int d = wq; d < n_dm; d += WPP) {
+      const int dl_cur = dl_next;
+      const int dmax_d = __builtin_amdgcn_readfirstlane(dmax_next);
+      const int dn = d + WPP;
+      dl_next = (dn < n_dm && l < n_sub) ? cd.delays[dn * n_sub + l] : 0;
+      dmax_next = dn < n_dm ? cd.dmax[dn] : 0;
       rep.d = d;
-      if (cd.dmax[d] >= n_t) {
+      if (dmax_d >= n_t) {
         for (int iw = 0; iw < NSFRB_NW; ++iw) rep.invalid(iw);
         rep.flush();
         continue;
@@ -273,7 +295,8 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
         float cur[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) cur[c] = 0.f;
-        for (int s = 0; s < n_sub; ++s) add_row<C>(cur, zbase + s * rs, cd.delays[d * n_sub + s], l);
+        for (int s = 0; s < n_sub; ++s)
+          add_row<C>(cur, zbase + s * rs, __builtin_amdgcn_readlane(dl_cur, s), l);
         nsfrb_chain<C>(pass, cur, rep);
       }
       rep.flush();
@@ -300,17 +323,17 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
 
 // Single cube: work item i covers pixels [i*PIX, i*PIX + PIX); items are dealt
 // so that the items running on one XCD at a time are neighbours.
-template <int C, int PIX>
+template <int C, int PIX, int NW>
 __device__ __forceinline__ void search_cube(const nsfrb::CubeDesc& cd) {
   using namespace nsfrb;
   extern __shared__ unsigned char lds_raw[];
-  __shared__ Best red[kWaves];
+  __shared__ Best red[NW];
   ST* zl = reinterpret_cast<ST*>(lds_raw);
   const int n_items = (cd.n_pix + PIX - 1) / PIX;
   for (int blk = blockIdx.x; blk < n_items; blk += gridDim.x) {
     int item = blk;
     if ((n_items & 7) == 0 && (int)gridDim.x == n_items) item = (blk & 7) * (n_items >> 3) + (blk >> 3);
-    search_group<C, PIX>(cd, item * PIX, zl, red);
+    search_group<C, PIX, NW>(cd, item * PIX, zl, red);
   }
 }
 

@@ -56,7 +56,6 @@ static constexpr int kMaxWidth = 32;
 static constexpr int kMaxCand = 4096;
 static constexpr int kMaxAccumulators = 3;     // non-power-of-two widths open at once
 static constexpr size_t kLdsBudget = 160 * 1024 - 1024;
-static constexpr int kSearchThreads = 512;
 
 static size_t dtype_size(int dt) { return dt == DT_F32 ? 4 : 2; }
 
@@ -143,6 +142,7 @@ extern "C" nsfrb_status nsfrb_plan_delays(const nsfrb_search_config* cfg, int32_
 struct KernelClass {
   int C;     // samples per lane
   int PIX;   // pixels per workgroup
+  int NW;    // waves per workgroup (8 or 16)
 };
 std::string single_kernel_name(const KernelClass& k);
 // Samples per lane: odd, so 64 lanes reading rows at a common delay hit
@@ -254,18 +254,18 @@ static std::string gen_source(int store, int nw, int npass, const std::string& c
   o << "#include \"k_search_body.h\"\n";
   o << chain;
   for (const auto& k : single)
-    o << "extern \"C\" __global__ __launch_bounds__(512) void " << single_kernel_name(k)
-      << "(nsfrb::CubeDesc cd) { search_cube<" << k.C << ", " << k.PIX << ">(cd); }\n";
+    o << "extern \"C\" __global__ __launch_bounds__(" << 64 * k.NW << ") void " << single_kernel_name(k)
+      << "(nsfrb::CubeDesc cd) { search_cube<" << k.C << ", " << k.PIX << ", " << k.NW << ">(cd); }\n";
   // one persistent kernel per class of the batch: its workgroups take the work
   // items of that class's cubes (descriptors contiguous, item_begin relative)
   // from a device counter, one item at a time, until the counter passes n_items
   for (size_t i = 0; i < batch.size(); ++i)
-    o << "extern \"C\" __global__ __launch_bounds__(512) void nsfrb_batch_kernel_" << i
+    o << "extern \"C\" __global__ __launch_bounds__(" << 64 * batch[i].NW << ") void nsfrb_batch_kernel_" << i
       << "(const nsfrb::CubeDesc* __restrict__ descs, int n_cubes, long long n_items,"
          " unsigned long long* __restrict__ next_item) {\n"
          "  using namespace nsfrb;\n"
          "  extern __shared__ unsigned char lds_raw[];\n"
-         "  __shared__ Best red[kWaves];\n"
+         "  __shared__ Best red[" << batch[i].NW << "];\n"
          "  __shared__ long long item;\n"
          "  ST* zl = reinterpret_cast<ST*>(lds_raw);\n"
          "  for (;;) {\n"
@@ -275,14 +275,15 @@ static std::string gen_source(int store, int nw, int npass, const std::string& c
          "    __syncthreads();\n"
          "    if (it >= n_items) break;\n"
          "    const CubeDesc cd = descs[find_cube(descs, n_cubes, it)];\n"
-         "    search_group<" << batch[i].C << ", " << batch[i].PIX << ">(cd, (int)(it - cd.item_begin) * "
+         "    search_group<" << batch[i].C << ", " << batch[i].PIX << ", " << batch[i].NW
+      << ">(cd, (int)(it - cd.item_begin) * "
       << batch[i].PIX << ", zl, red);\n"
          "  }\n}\n";
   return o.str();
 }
 
 std::string single_kernel_name(const KernelClass& k) {
-  return "nsfrb_search_c" + std::to_string(k.C) + "_p" + std::to_string(k.PIX);
+  return "nsfrb_search_c" + std::to_string(k.C) + "_p" + std::to_string(k.PIX) + "_w" + std::to_string(k.NW);
 }
 
 // Compiled modules, shared by every handle on a device.
@@ -351,18 +352,23 @@ static int max_delay_searchable(const std::vector<int32_t>& delays, int n_dm, in
   return dmax_search;
 }
 
-// Pixels per workgroup that fit in LDS, best first by the default heuristic
-// (enough waves per pixel to cover the DM trials).
-static std::vector<int> pix_candidates(int n_dm, int n_sub, int rs, int store) {
-  std::vector<int> out;
+// Kernel shapes that fit in LDS, best first by the default heuristic (enough
+// waves per pixel to cover the DM trials): PIX pixels per workgroup of 8
+// waves, and one or two pixels per workgroup of 16 waves. A single large
+// workgroup may take most of a CU's LDS, so 16 waves of one workgroup reach an
+// occupancy that two 8-wave workgroups with that much LDS do not.
+static std::vector<KernelClass> plan_candidates(int C, int n_dm, int n_sub, int rs, int store) {
+  std::vector<KernelClass> out;
   for (int pix : {1, 2, 4, 8})
-    if (lds_bytes_for(pix, n_sub, rs, store) <= kLdsBudget) out.push_back(pix);
-  std::sort(out.begin(), out.end(), [&](int a, int b) {
-    const int wa = 8 / a, wb = 8 / b;           // waves per pixel
+    if (lds_bytes_for(pix, n_sub, rs, store) <= kLdsBudget) out.push_back({C, pix, 8});
+  std::sort(out.begin(), out.end(), [&](const KernelClass& a, const KernelClass& b) {
+    const int wa = 8 / a.PIX, wb = 8 / b.PIX;     // waves per pixel
     const bool fa = wa <= n_dm, fb = wb <= n_dm;  // no idle waves
     if (fa != fb) return fa;
-    return fa ? a < b : a > b;
+    return fa ? a.PIX < b.PIX : a.PIX > b.PIX;
   });
+  for (int pix : {1, 2})
+    if (lds_bytes_for(pix, n_sub, rs, store) <= kLdsBudget && 16 / pix <= n_dm) out.push_back({C, pix, 16});
   return out;
 }
 
@@ -375,16 +381,14 @@ extern "C" int nsfrb_debug_plan_source(const nsfrb_search_config* cfg, char* out
   const int dmax_search = max_delay_searchable(dl, cfg->n_dm, cfg->n_sub, cfg->n_time, nullptr);
   const int C = samples_per_lane(cfg->n_time, cfg->store_dtype);
   const int rs = row_len(C, dmax_search, cfg->store_dtype);
-  std::vector<int> pix = pix_candidates(cfg->n_dm, cfg->n_sub, rs, cfg->store_dtype);
-  if (pix.empty()) {
+  std::vector<KernelClass> ks = plan_candidates(C, cfg->n_dm, cfg->n_sub, rs, cfg->store_dtype);
+  if (ks.empty()) {
     fail(NSFRB_ERR_UNSUPPORTED, "a pixel's rows do not fit in LDS");
     return -1;
   }
   std::string chain;
   int npass = 1;
   if (gen_chain(std::vector<int>(cfg->width, cfg->width + cfg->n_width), chain, &npass) != NSFRB_OK) return -1;
-  std::vector<KernelClass> ks;
-  for (int p : pix) ks.push_back({C, p});
   const std::string src = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, ks);
   if (out && cap > 0) std::snprintf(out, (size_t)cap, "%s", src.c_str());
   if (compile) {
@@ -400,12 +404,12 @@ struct nsfrb_search {
   std::vector<double> freqs, dms;
   std::vector<int32_t> widths, delays, dmaxv;
   int n_pix = 0, device = 0;
-  int C = 0, rs = 0, pix = 1;          // chosen kernel class and LDS row length
+  int C = 0, rs = 0, pix = 1, nw = 8;  // chosen kernel class and LDS row length
   size_t lds_bytes = 0;
   std::string source;                  // generated search translation unit
   hipModule_t mod = nullptr;
   hipFunction_t search_fn = nullptr;
-  std::vector<int> tuned_pix;          // candidates timed by the autotuner
+  std::vector<KernelClass> tuned;      // candidates timed by the autotuner
   std::vector<float> tuned_ms;
   // device buffers
   int32_t *d_delays = nullptr, *d_dmax = nullptr;
@@ -451,7 +455,7 @@ static void release(nsfrb_search* h) {
   delete h;
 }
 
-static nsfrb_status autotune(nsfrb_search* h, const std::vector<int>& pix);
+static nsfrb_status autotune(nsfrb_search* h, const std::vector<KernelClass>& ks);
 
 extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfrb_search** out) {
   g_last_error.clear();
@@ -473,15 +477,13 @@ extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfr
   const int dmax_search = max_delay_searchable(h->delays, cfg->n_dm, cfg->n_sub, cfg->n_time, &h->dmaxv);
   h->C = samples_per_lane(cfg->n_time, cfg->store_dtype);
   h->rs = row_len(h->C, dmax_search, cfg->store_dtype);
-  std::vector<int> pix = pix_candidates(cfg->n_dm, cfg->n_sub, h->rs, cfg->store_dtype);
-  if (pix.empty())
+  std::vector<KernelClass> ks = plan_candidates(h->C, cfg->n_dm, cfg->n_sub, h->rs, cfg->store_dtype);
+  if (ks.empty())
     return fail(NSFRB_ERR_UNSUPPORTED, "n_sub x (padded n_time + max delay) does not fit in LDS for this store dtype");
   std::string chain;
   int npass = 1;
   st = gen_chain(h->widths, chain, &npass);
   if (st != NSFRB_OK) return st;
-  std::vector<KernelClass> ks;
-  for (int p : pix) ks.push_back({h->C, p});
   h->source = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, {});
   const char* force = std::getenv("NSFRB_FORCE_ALLOC_FAIL");
   if (force && std::atoi(force) != 0) return fail(NSFRB_ERR_OUT_OF_MEMORY, "allocation failure forced by NSFRB_FORCE_ALLOC_FAIL");
@@ -522,7 +524,7 @@ extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfr
   HIP_TRY(hipMemcpy(h->d_dmax, h->dmaxv.data(), h->dmaxv.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->d_norms, norms.data(), norms.size() * sizeof(float), hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(h->d_flags, 0, sizeof(unsigned long long)));
-  st = autotune(h.get(), pix);
+  st = autotune(h.get(), ks);
   if (st != NSFRB_OK) return st;
   h->lds_bytes = lds_bytes_for(h->pix, cfg->n_sub, h->rs, cfg->store_dtype);
   *out = h.release();
@@ -562,18 +564,18 @@ static CubeDescHost cube_desc(const nsfrb_search* h, const void* z, int n_pix) {
   return d;
 }
 
-static nsfrb_status launch_search_fn(const nsfrb_search* h, hipFunction_t fn, int pix, const void* z, int n_pix,
-                                     hipStream_t st) {
+static nsfrb_status launch_search_fn(const nsfrb_search* h, hipFunction_t fn, const KernelClass& k, const void* z,
+                                     int n_pix, hipStream_t st) {
   CubeDescHost d = cube_desc(h, z, n_pix);
   void* args[] = {(void*)&d};
-  const unsigned n_items = (unsigned)((n_pix + pix - 1) / pix);
-  const size_t lds = lds_bytes_for(pix, h->cfg.n_sub, h->rs, h->cfg.store_dtype);
-  HIP_TRY(hipModuleLaunchKernel(fn, n_items, 1, 1, kSearchThreads, 1, 1, (unsigned)lds, st, args, nullptr));
+  const unsigned n_items = (unsigned)((n_pix + k.PIX - 1) / k.PIX);
+  const size_t lds = lds_bytes_for(k.PIX, h->cfg.n_sub, h->rs, h->cfg.store_dtype);
+  HIP_TRY(hipModuleLaunchKernel(fn, n_items, 1, 1, 64 * k.NW, 1, 1, (unsigned)lds, st, args, nullptr));
   return NSFRB_OK;
 }
 
 static nsfrb_status launch_search(const nsfrb_search* h, const void* z, hipStream_t st) {
-  return launch_search_fn(h, h->search_fn, h->pix, z, h->n_pix, st);
+  return launch_search_fn(h, h->search_fn, {h->C, h->pix, h->nw}, z, h->n_pix, st);
 }
 
 // Autotuner: time every pixels-per-workgroup candidate on this plan's shape
@@ -589,17 +591,24 @@ struct TuneKey {
   }
 };
 static std::mutex g_tune_mu;
-static std::map<TuneKey, int> g_tune_cache;
+static std::map<TuneKey, std::pair<int, int>> g_tune_cache;   // (pixels, waves) per workgroup
 
-static nsfrb_status autotune(nsfrb_search* h, const std::vector<int>& pix) {
+static nsfrb_status autotune(nsfrb_search* h, const std::vector<KernelClass>& ks) {
   const nsfrb_search_config& c = h->cfg;
-  std::vector<hipFunction_t> fns(pix.size());
-  for (size_t i = 0; i < pix.size(); ++i)
-    HIP_TRY(hipModuleGetFunction(&fns[i], h->mod, single_kernel_name({h->C, pix[i]}).c_str()));
-  h->pix = pix[0];
-  h->search_fn = fns[0];
+  std::vector<hipFunction_t> fns(ks.size());
+  for (size_t i = 0; i < ks.size(); ++i)
+    HIP_TRY(hipModuleGetFunction(&fns[i], h->mod, single_kernel_name(ks[i]).c_str()));
+  auto choose = [&](size_t i) { h->pix = ks[i].PIX; h->nw = ks[i].NW; h->search_fn = fns[i]; };
+  choose(0);
+  // NSFRB_PLAN="pixels,waves" picks that shape when it is a candidate (for tuning studies)
+  if (const char* plan = std::getenv("NSFRB_PLAN")) {
+    int pp = 0, ww = 0;
+    if (std::sscanf(plan, "%d,%d", &pp, &ww) == 2)
+      for (size_t i = 0; i < ks.size(); ++i)
+        if (ks[i].PIX == pp && ks[i].NW == ww) { choose(i); return NSFRB_OK; }
+  }
   const char* env = std::getenv("NSFRB_AUTOTUNE");
-  if (pix.size() == 1 || (env && std::atoi(env) == 0)) return NSFRB_OK;
+  if (ks.size() == 1 || (env && std::atoi(env) == 0)) return NSFRB_OK;
   int bucket = 0;
   while ((1 << bucket) < h->n_pix) ++bucket;
   TuneKey key{h->C, c.n_sub, c.n_time, c.n_dm, bucket > 13 ? 13 : bucket, c.store_dtype, h->widths};
@@ -607,8 +616,8 @@ static nsfrb_status autotune(nsfrb_search* h, const std::vector<int>& pix) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      for (size_t i = 0; i < pix.size(); ++i)
-        if (pix[i] == it->second) { h->pix = pix[i]; h->search_fn = fns[i]; }
+      for (size_t i = 0; i < ks.size(); ++i)
+        if (ks[i].PIX == it->second.first && ks[i].NW == it->second.second) choose(i);
       return NSFRB_OK;
     }
   }
@@ -622,28 +631,35 @@ static nsfrb_status autotune(nsfrb_search* h, const std::vector<int>& pix) {
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  float best_ms = 1e30f;
-  for (size_t i = 0; i < pix.size(); ++i) {
-    nsfrb_status st = launch_search_fn(h, fns[i], pix[i], zt, n_tune, nullptr);   // warm-up
-    if (st != NSFRB_OK) return st;
-    HIP_TRY(hipEventRecord(e0, nullptr));
-    for (int r = 0; r < 3; ++r) {
-      st = launch_search_fn(h, fns[i], pix[i], zt, n_tune, nullptr);
+  // candidates are timed in interleaved rounds and each keeps its best round, so
+  // clock ramp-up after an idle spell (e.g. the plan compile) favours none of them
+  std::vector<float> ms_best(ks.size(), 1e30f);
+  for (int round = 0; round < 3; ++round) {
+    for (size_t i = 0; i < ks.size(); ++i) {
+      nsfrb_status st = launch_search_fn(h, fns[i], ks[i], zt, n_tune, nullptr);   // warm-up
       if (st != NSFRB_OK) return st;
+      HIP_TRY(hipEventRecord(e0, nullptr));
+      for (int r = 0; r < 2; ++r) {
+        st = launch_search_fn(h, fns[i], ks[i], zt, n_tune, nullptr);
+        if (st != NSFRB_OK) return st;
+      }
+      HIP_TRY(hipEventRecord(e1, nullptr));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      ms_best[i] = std::min(ms_best[i], ms / 2.f);
     }
-    HIP_TRY(hipEventRecord(e1, nullptr));
-    HIP_TRY(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    ms /= 3.f;
-    h->tuned_pix.push_back(pix[i]);
-    h->tuned_ms.push_back(ms);
-    if (ms < best_ms) { best_ms = ms; h->pix = pix[i]; h->search_fn = fns[i]; }
+  }
+  float best_ms = 1e30f;
+  for (size_t i = 0; i < ks.size(); ++i) {
+    h->tuned.push_back(ks[i]);
+    h->tuned_ms.push_back(ms_best[i]);
+    if (ms_best[i] < best_ms) { best_ms = ms_best[i]; choose(i); }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune_cache[key] = h->pix;
+  g_tune_cache[key] = {h->pix, h->nw};
   return NSFRB_OK;
 }
 
@@ -819,6 +835,7 @@ extern "C" nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* i
   info[1] = h->pix;
   info[2] = h->rs;
   info[3] = (int32_t)h->lds_bytes;
+  info[4] = 64 * h->nw;
   return NSFRB_OK;
 }
 
@@ -896,11 +913,11 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
     nsfrb_search* h = b->cubes[i];
     int cls = -1;
     for (size_t k = 0; k < b->classes.size(); ++k)
-      if (b->classes[k].k.C == h->C && b->classes[k].k.PIX == h->pix) cls = (int)k;
+      if (b->classes[k].k.C == h->C && b->classes[k].k.PIX == h->pix && b->classes[k].k.NW == h->nw) cls = (int)k;
     if (cls < 0) {
       cls = (int)b->classes.size();
       b->classes.emplace_back();
-      b->classes.back().k = {h->C, h->pix};
+      b->classes.back().k = {h->C, h->pix, h->nw};
     }
     cls_of[i] = cls;
   }
@@ -938,7 +955,7 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
     HIP_TRY(hipModuleGetFunction(&bc.fn, b->mod, ("nsfrb_batch_kernel_" + std::to_string(c)).c_str()));
     // a persistent grid of as many workgroups as this class's kernel keeps resident
     int per_cu = 0;
-    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bc.fn, kSearchThreads, bc.lds));
+    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bc.fn, 64 * bc.k.NW, bc.lds));
     const long long g = (long long)n_cu * std::max(1, per_cu);
     bc.grid = (unsigned)std::max(1LL, std::min(g, bc.n_items));
   }
@@ -1009,7 +1026,7 @@ static nsfrb_status batch_enqueue(nsfrb_batch* b, const void* const* d_cubes, hi
     unsigned long long* next = b->d_next + c;
     HIP_TRY(launch_zero_u64(next, st));
     void* args[] = {(void*)&descs, &n, &items, (void*)&next};
-    HIP_TRY(hipModuleLaunchKernel(bc.fn, bc.grid, 1, 1, kSearchThreads, 1, 1, (unsigned)bc.lds, st, args, nullptr));
+    HIP_TRY(hipModuleLaunchKernel(bc.fn, bc.grid, 1, 1, 64 * bc.k.NW, 1, 1, (unsigned)bc.lds, st, args, nullptr));
   }
   return batch_candidates(b, st);
 }

@@ -329,10 +329,10 @@ class Search:
         return out
 
     def plan_info(self):
-        out = np.zeros(4, np.int32)
+        out = np.zeros(5, np.int32)
         check(lib().nsfrb_search_plan_info(self.h, _ptr(out, ctypes.c_int32)))
         return dict(samples_per_lane=int(out[0]), pixels_per_workgroup=int(out[1]), row_len=int(out[2]),
-                    lds_bytes=int(out[3]))
+                    lds_bytes=int(out[3]), threads_per_workgroup=int(out[4]))
 
 
 class Batch:
