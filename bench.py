@@ -79,6 +79,67 @@ def load_traffic(kernel):
     return rec.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
 
 
+def copy_probe(nbytes, reps=3):
+    """A plain device-to-device copy of known size (the runtime's copy kernel),
+    run under the same rocprofv3 counters as the search to calibrate them."""
+    import ctypes
+    from paper_2510_18136_amd import hip
+    a, b = hip.Buffer(nbytes).zero(), hip.Buffer(nbytes)
+    for _ in range(reps):
+        hip.check(hip.lib().hipMemcpy(ctypes.c_void_p(b.ptr), ctypes.c_void_p(a.ptr), nbytes, 3), "hipMemcpy D2D")
+    hip.synchronize()
+    a.close()
+    b.close()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes):
+    """HBM bytes per launch of each kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+    runs (KiB per dispatch), each scaled by what the same counter reads for a copy
+    of copy_bytes; written to profiles/hbm_traffic.json with the kernel source hash."""
+    import csv
+    from collections import defaultdict
+
+    def per_kernel(path, counter):
+        """counter values of each kernel's largest-grid dispatches (the workload's own
+        launches, not the autotuner's timing launches on a smaller cube)"""
+        acc = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                acc[r["Kernel_Name"]].append((int(r["Grid_Size"]), float(r["Counter_Value"])))
+        return {k: [v for g, v in xs if g == max(g2 for g2, _ in xs)] for k, xs in acc.items()}
+
+    def copy_kib(path, counter):
+        v = [x for k, xs in per_kernel(path, counter).items() if "copyBuffer" in k for x in xs]
+        return max(v)                                 # the large D2D copies (small copies are uploads)
+
+    f_scale = copy_bytes / (copy_kib(copy_fetch_csv, "FETCH_SIZE") * 1024.0)
+    w_scale = copy_bytes / (copy_kib(copy_write_csv, "WRITE_SIZE") * 1024.0)
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    # search kernels that only ran as the autotuner's candidates (on its smaller cube) are left out
+    grids = defaultdict(int)
+    for r in csv.DictReader(open(fetch_csv)):
+        grids[r["Kernel_Name"]] = max(grids[r["Kernel_Name"]], int(r["Grid_Size"]))
+    full = max((g for k, g in grids.items() if k.startswith("nsfrb_search_c")), default=0)
+    kernels = {}
+    for k in fetch:
+        if k not in write or not (k.startswith("nsfrb_search_c") or "k_stats_norm" in k):
+            continue
+        if k.startswith("nsfrb_search_c") and grids[k] < full:
+            continue
+        fb = float(np.median(fetch[k])) * 1024.0 * f_scale
+        wb = float(np.median(write[k])) * 1024.0 * w_scale
+        name = k if k.startswith("nsfrb_search_c") else "k_stats_norm"
+        kernels[name] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                         "dispatches": len(fetch[k])}
+    rec = {"source_hash": kernel_source_hash(), "copy_probe_bytes": copy_bytes,
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": kernels}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def cpu_baseline(cube, meta, target_s=12.0):
     """Time the FP64 oracle on a bounded pixel sample of the same workload."""
     from oracle import search as osr
@@ -215,7 +276,18 @@ def main():
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-classifier", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV",
+                                                        "COPY_BYTES"),
+                    help="write profiles/hbm_traffic.json from rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from_counters(*args.traffic_from[:4], int(args.traffic_from[4]))
+        return
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the search is built and "
               f"measured on a single MI355X).", file=sys.stderr)
@@ -276,12 +348,15 @@ def main():
     delays = cfg.delays()
     by, ops = algorithmic_counts(n_pix, 16, cube.shape[0], delays, meta["widths"], 4)
     t_search = stages[1] * 1e-3
-    traffic = load_traffic("nsfrb_search_kernel")
+    plan32 = s32.plan_info()
+    kname = (f"nsfrb_search_c{plan32['samples_per_lane']}_p{plan32['pixels_per_workgroup']}"
+             f"_w{plan32['threads_per_workgroup'] // 64}")
+    traffic = load_traffic(kname)
     roof = {"bound": "alu", "achieved": ops / t_search / 1e12, "peak": PEAK_ALU_TOPS, "unit": "TFLOP/s",
             "frac": ops / t_search / 1e12 / PEAK_ALU_TOPS, "traffic": traffic,
-            "kernel": "nsfrb_search_kernel", "ms_per_launch": stages[1],
+            "kernel": kname, "ms_per_launch": stages[1],
             "algorithmic_ops_per_launch": ops, "algorithmic_bytes_per_launch": by}
-    hbm = {"kernel": "nsfrb_search_kernel", "achieved_GBs": by / t_search / 1e9, "peak_GBs": PEAK_HBM_GBS,
+    hbm = {"kernel": kname, "achieved_GBs": by / t_search / 1e9, "peak_GBs": PEAK_HBM_GBS,
            "frac": by / t_search / 1e9 / PEAK_HBM_GBS,
            "stats_kernel_GBs": (n_pix * 16 * 2048 * (4 + 4) + n_pix * 16 * 16) / (stages[0] * 1e-3) / 1e9}
     out = {"metric": "pixel*DM*width trials/s (+ HBM GB/s %peak of the search kernel)",
@@ -293,7 +368,7 @@ def main():
                                   "100 pulses, 20 zero-DM spikes, 2 stripes (seed 2)",
                       "pixels": n_pix, "sub_bands": 16, "samples": 2048, "dm_trials": n_dm, "widths": n_w},
            "stage_ms": {"stats_norm": stages[0], "search": stages[1], "candidates": stages[2]},
-           "roofline": roof, "hbm": hbm, "candidates_found": ntot, "search_plan": s32.plan_info()}
+           "roofline": roof, "hbm": hbm, "candidates_found": ntot, "search_plan": plan32}
     s32.close()
     if not args.no_fp16:
         cfg16, s16 = make("f16")
