@@ -38,9 +38,15 @@
 
 namespace nsfrb {
 
-// Waves per workgroup (= pixels per tile): 16 for short series; 8 for long ones,
-// which need more than 128 VGPRs per wave.
-template <int V> struct StatShape { static constexpr int kWaves = V >= 32 ? 8 : 16; };
+// Waves per workgroup (= pixels per tile): 16 for short series, 8 for long
+// ones (the LDS rows of 16 series of 2048 samples would not leave room for a
+// second workgroup on the CU).
+template <int V> struct StatShape {
+  static constexpr int kWaves = V >= 32 ? 8 : 16;
+  // two workgroups per CU (8 waves each) for series up to 2048 samples: at most
+  // 128 VGPRs; longer series fill the CU's LDS with one workgroup
+  static constexpr int kMinWavesPerEU = V <= 32 ? 4 : 1;
+};
 constexpr double kMadToSigma = 1.482602218505602;
 
 struct SeriesCtx {
@@ -56,16 +62,36 @@ struct Sel {
   int rank_in_ties;
 };
 
-// k-th smallest (0-based) of the FP32 keys key[j]. Registers past the end of
+// Keys of a series seen through an accessor key(j), j = 0..V-1 (sample
+// 64 j + lane): FP32 registers, or the series itself in LDS.
+template <int V>
+struct RegKeys {
+  const float (&a)[V];
+  __device__ __forceinline__ float operator()(int j) const { return a[j]; }
+};
+struct LdsSeries {
+  const float* x;     // this wave's series, sample t at x[t]
+  int l;
+  __device__ __forceinline__ float operator()(int j) const { return x[64 * j + l]; }
+};
+// FP32-rounded distances |x - med| (FP64 difference), formed from the LDS
+// series on each read instead of being held in registers.
+struct DistKeys {
+  LdsSeries x;
+  double med;
+  __device__ __forceinline__ float operator()(int j) const { return (float)fabs((double)x(j) - med); }
+};
+
+// k-th smallest (0-based) of the FP32 keys key(j). Registers past the end of
 // the series hold NaN, which fails every comparison and is ignored by
 // fminf/fmaxf, so they never take part.
-template <int V>
-__device__ __forceinline__ Sel select_kth_f32(const float (&key)[V], int k, const SeriesCtx& cx) {
+template <int V, class Key>
+__device__ __forceinline__ Sel select_kth_f32(const Key& key, int k, const SeriesCtx& cx) {
   const int l = lane_id();
   float lo = __builtin_inff(), hi = -__builtin_inff();
 #pragma unroll
   for (int j = 0; j < V; ++j)
-    { lo = fminf(lo, key[j]); hi = fmaxf(hi, key[j]); }
+    { lo = fminf(lo, key(j)); hi = fmaxf(hi, key(j)); }
   lo = wave_min_f(lo);
   hi = wave_max_f(hi);
   int krem = k;                                    // rank among keys in [lo, hi]
@@ -77,7 +103,7 @@ __device__ __forceinline__ Sel select_kth_f32(const float (&key)[V], int k, cons
     wave_lds_sync();
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-      const float v = key[j];
+      const float v = key(j);
       if (v >= lo && v <= hi) {
         int b = (int)((v - lo) * scale);
         b = b > 255 ? 255 : b;
@@ -107,7 +133,7 @@ __device__ __forceinline__ Sel select_kth_f32(const float (&key)[V], int k, cons
       int base = 0;
 #pragma unroll
       for (int j = 0; j < V; ++j) {
-        const float v = key[j];
+        const float v = key(j);
         bool mem = false;
         if (v >= lo && v <= hi) {
           int b = (int)((v - lo) * scale);
@@ -130,7 +156,7 @@ __device__ __forceinline__ Sel select_kth_f32(const float (&key)[V], int k, cons
     float nlo = __builtin_inff(), nhi = -__builtin_inff();
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-      const float v = key[j];
+      const float v = key(j);
       if (v >= lo && v <= hi) {
         int b = (int)((v - lo) * scale);
         b = b > 255 ? 255 : b;
@@ -147,7 +173,7 @@ __device__ __forceinline__ Sel select_kth_f32(const float (&key)[V], int k, cons
     float nxt = __builtin_inff();
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-      const float v = key[j];
+      const float v = key(j);
       ceq += (v == cur);
       if (v > cur) nxt = fminf(nxt, v);
     }
@@ -161,14 +187,14 @@ __device__ __forceinline__ Sel select_kth_f32(const float (&key)[V], int k, cons
 
 // The (rank)-th and (rank+1)-th smallest FP64 values val(j) among the samples
 // whose key equals kv; `second` is +inf when there is no (rank+1)-th tie.
-template <int V, class Val>
-__device__ __forceinline__ void resolve_ties(const float (&key)[V], float kv, int rank, const Val& val,
+template <int V, class Key, class Val>
+__device__ __forceinline__ void resolve_ties(const Key& key, float kv, int rank, const Val& val,
                                              const SeriesCtx& cx, double& first, double& second) {
   const int l = lane_id();
   int base = 0;
 #pragma unroll
   for (int j = 0; j < V; ++j) {
-    const bool mem = key[j] == kv;
+    const bool mem = key(j) == kv;
     const uint64_t mm = ballot(mem);
     if (mem) {
       const int pos = base + lanes_below(mm);
@@ -192,7 +218,7 @@ __device__ __forceinline__ void resolve_ties(const float (&key)[V], float kv, in
     double nxt = __builtin_inf();
 #pragma unroll
     for (int j = 0; j < V; ++j)
-      if (key[j] == kv) {
+      if (key(j) == kv) {
         const double v = val(j);
         if (v > cur) nxt = fmin(nxt, v);
       }
@@ -201,7 +227,7 @@ __device__ __forceinline__ void resolve_ties(const float (&key)[V], float kv, in
     int ceq = 0;
 #pragma unroll
     for (int j = 0; j < V; ++j)
-      if (key[j] == kv) ceq += (val(j) == cur);
+      if (key(j) == kv) ceq += (val(j) == cur);
     ceq = wave_sum(ceq);
     if (have_first) { second = cur; return; }
     if (rank < ceq) {
@@ -215,20 +241,20 @@ __device__ __forceinline__ void resolve_ties(const float (&key)[V], float kv, in
 }
 
 // Smallest key strictly above kv (+inf if none).
-template <int V>
-__device__ __forceinline__ float next_key(const float (&key)[V], float kv, int n_t) {
+template <int V, class Key>
+__device__ __forceinline__ float next_key(const Key& key, float kv, int n_t) {
   const int l = lane_id();
   float m = __builtin_inff();
 #pragma unroll
   for (int j = 0; j < V; ++j)
-    if (key[j] > kv) m = fminf(m, key[j]);
+    if (key(j) > kv) m = fminf(m, key(j));
   return wave_min_f(m);
 }
 
-// FP64 median of val(j) given FP32 keys with key[j] = RN32(val(j)) (rounding
+// FP64 median of val(j) given FP32 keys with key(j) = RN32(val(j)) (rounding
 // is monotone); when kExact, the keys are the values themselves.
-template <bool kExact, int V, class Val>
-__device__ __forceinline__ double median_via_keys(const float (&key)[V], const Val& val, const SeriesCtx& cx) {
+template <bool kExact, int V, class Key, class Val>
+__device__ __forceinline__ double median_via_keys(const Key& key, const Val& val, const SeriesCtx& cx) {
   const int n = cx.n_t;
   const int k1 = (n - 1) / 2;
   const Sel s = select_kth_f32<V>(key, k1, cx);
@@ -240,7 +266,7 @@ __device__ __forceinline__ double median_via_keys(const float (&key)[V], const V
     const int l = lane_id();
     int ceq = 0;
 #pragma unroll
-    for (int j = 0; j < V; ++j) ceq += key[j] == s.key;
+    for (int j = 0; j < V; ++j) ceq += key(j) == s.key;
     ceq = wave_sum(ceq);
     b = (s.rank_in_ties + 1 < ceq) ? a : (double)next_key<V>(key, s.key, n);
   } else {
@@ -261,18 +287,20 @@ __device__ __forceinline__ double div_markstein(double a, double b, double r) {
   return __builtin_fma(e, r, q0);
 }
 
-// Statistics + normalisation of one series held as xv[j] <-> t = 64 j + lane.
+// Statistics + normalisation of one series held in LDS (sample t at xs[t];
+// NaN from n_t up to 64 V), read as x(j) <-> t = 64 j + lane.
 template <int V, typename ST>
-__device__ __forceinline__ void process_series(const float (&xv)[V], int p, int s, int n_t, int n_sub, int mode,
+__device__ __forceinline__ void process_series(const float* xs, int p, int s, int n_t, int n_sub, int mode,
                                                const double* __restrict__ med_in, const double* __restrict__ sig_in,
                                                double* __restrict__ med_out, double* __restrict__ sig_out,
                                                ST* __restrict__ z, unsigned long long* __restrict__ flag_count,
                                                const SeriesCtx& cx) {
   const int l = lane_id();
+  const LdsSeries x{xs, l};
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < V; ++j)
-    if (64 * j + l < n_t && !__builtin_isfinite(xv[j])) bad = true;
+    if (64 * j + l < n_t && !__builtin_isfinite(x(j))) bad = true;
   const bool any_bad = ballot(bad) != 0;
 
   long long nflag = 0;
@@ -282,18 +310,15 @@ __device__ __forceinline__ void process_series(const float (&xv)[V], int p, int 
     if (any_bad) {
       med = __builtin_nan(""); sig = __builtin_nan(""); usable = false;
     } else {
-      auto vx = [&](int j) { return (double)xv[j]; };
-      med = median_via_keys<true, V>(xv, vx, cx);
+      auto vx = [&](int j) { return (double)x(j); };
+      med = median_via_keys<true, V>(x, vx, cx);
       // separate copies of the median for each use, so the compiler recomputes the
       // FP64 differences instead of keeping all of them live
       double mk = med, mv = med;
       asm volatile("" : "+v"(mk));
       asm volatile("" : "+v"(mv));
-      float dk[V];
-#pragma unroll
-      for (int j = 0; j < V; ++j) dk[j] = (float)fabs((double)xv[j] - mk);
-      auto vd = [&](int j) { return fabs((double)xv[j] - mv); };
-      const double mad = median_via_keys<false, V>(dk, vd, cx);
+      auto vd = [&](int j) { return fabs((double)x(j) - mv); };
+      const double mad = median_via_keys<false, V>(DistKeys{x, mk}, vd, cx);
       sig = kMadToSigma * mad;
       usable = (sig > 0.0) && (sig < __builtin_inf());
     }
@@ -318,9 +343,10 @@ __device__ __forceinline__ void process_series(const float (&xv)[V], int p, int 
     const int t = 64 * j + l;
     if (t < n_t) {
       float zf;
-      const bool fin = __builtin_isfinite(xv[j]);
+      const float xj = x(j);
+      const bool fin = __builtin_isfinite(xj);
       if (mode == NORM_NONE) {
-        zf = fin ? xv[j] : 0.0f;
+        zf = fin ? xj : 0.0f;
         nbad_samples += !fin;
       } else if (!usable) {
         zf = 0.0f;
@@ -328,7 +354,7 @@ __device__ __forceinline__ void process_series(const float (&xv)[V], int p, int 
         zf = 0.0f;
         nbad_samples += 1;
       } else {
-        const double a = (double)xv[j] - med;
+        const double a = (double)xj - med;
         zf = (float)(fast_div ? div_markstein(a, sig, r) : a / sig);
       }
       zrow[t] = from_f32<ST>(zf);
@@ -340,17 +366,20 @@ __device__ __forceinline__ void process_series(const float (&xv)[V], int p, int 
 }
 
 template <int V, typename InT, typename ST>
-__global__ __launch_bounds__(StatShape<V>::kWaves * kWave) void k_stats_norm(
+__global__ __launch_bounds__(StatShape<V>::kWaves * kWave)
+__attribute__((amdgpu_waves_per_eu(StatShape<V>::kMinWavesPerEU))) void k_stats_norm(
     const InT* __restrict__ x, int n_t, int n_sub, int n_pix, int mode,
     const double* __restrict__ med_in, const double* __restrict__ sig_in,
     double* __restrict__ med_out, double* __restrict__ sig_out,
     ST* __restrict__ z, unsigned long long* __restrict__ flag_count) {
   constexpr int kStatWaves = StatShape<V>::kWaves;
-  constexpr int kStatTilePix = kStatWaves;        // one pixel per wave
-  constexpr int VC = V < 4 ? V : 4;               // registers filled per LDS chunk
-  constexpr int CT = 64 * VC;                     // samples per chunk
-  constexpr int RS = kStatTilePix + 1;            // padded LDS row
-  __shared__ float tile[CT * RS];
+  constexpr int kStatTilePix = kStatWaves;        // one pixel (series) per wave
+  // each wave's series lives in LDS, sample t at row[t]; rows are padded so that
+  // the load's stores (kStatTilePix pixels x 64/kStatTilePix times per wave
+  // instruction) fall in distinct banks, and a wave's reads of 64 consecutive
+  // samples are conflict-free anyway
+  constexpr int RS = 64 * V + 64 / kStatTilePix;
+  __shared__ float series[kStatWaves * RS];
   __shared__ uint32_t hist_all[kStatWaves][256];
   __shared__ double list_all[kStatWaves][64];
 
@@ -363,49 +392,36 @@ __global__ __launch_bounds__(StatShape<V>::kWaves * kWave) void k_stats_norm(
   if ((n_items & 7u) == 0) item = (item & 7u) * (n_items >> 3) + (item >> 3);
   const int s = (int)(item / gridDim.x);
   const int p0 = (int)(item % gridDim.x) * kStatTilePix;
-  const int w = threadIdx.x / kWave;
-  const int l = lane_id();
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const size_t plane = (size_t)n_sub * n_pix;
 
-  // this wave's pixel: p0 + w
-  float xa[V];
   // ---- load: rows of kStatTilePix pixels; every global load of the thread is
-  // issued first (one memory latency), then each chunk is transposed through LDS
-  constexpr int kPer = CT * kStatTilePix / (kStatWaves * kWave);   // values per thread per chunk
-  static_assert(kPer * kStatWaves * kWave == CT * kStatTilePix, "chunk must split evenly over the threads");
-  // thread i of a chunk reads pixel p0 + i % kStatTilePix of time row i / kStatTilePix;
-  // rows beyond n_t and pixels beyond n_pix load a valid address and become NaN
+  // issued first (one memory latency), then stored into the pixels' LDS rows.
+  // Thread i reads pixel p0 + i % kStatTilePix of time rows i / kStatTilePix +
+  // q * kRowStep; rows beyond n_t and pixels beyond n_pix load a valid address
+  // and become NaN.
+  constexpr int kRowStep = kStatWaves * kWave / kStatTilePix;       // = 64
+  constexpr int kPer = 64 * V / kRowStep;                           // loads per thread
   const int c_ld = threadIdx.x % kStatTilePix;
   const bool pix_ok = p0 + c_ld < n_pix;
   const InT* src = x + (size_t)s * n_pix + (pix_ok ? p0 + c_ld : 0);
-  constexpr int kRowStep = kStatWaves * kWave / kStatTilePix;      // time rows between q and q + 1
   const int r0 = threadIdx.x / kStatTilePix;
-  float stage[V / VC][kPer];
+  float stage[kPer];
 #pragma unroll
-  for (int ch = 0; ch < V / VC; ++ch) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int t = ch * CT + q * kRowStep + r0;
-      const bool ok = pix_ok && t < n_t;
-      const float v = to_f32(src[(size_t)(ok ? t : 0) * plane]);
-      stage[ch][q] = ok ? v : __builtin_nanf("");
-    }
+  for (int q = 0; q < kPer; ++q) {
+    const int t = q * kRowStep + r0;
+    const bool ok = pix_ok && t < n_t;
+    const float v = to_f32(src[(size_t)(ok ? t : 0) * plane]);
+    stage[q] = ok ? v : __builtin_nanf("");
   }
+  float* my_row = series + c_ld * RS + r0;
 #pragma unroll
-  for (int ch = 0; ch < V / VC; ++ch) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int i = threadIdx.x + q * kStatWaves * kWave;
-      tile[(i / kStatTilePix) * RS + i % kStatTilePix] = stage[ch][q];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int jj = 0; jj < VC; ++jj) xa[ch * VC + jj] = tile[(64 * jj + l) * RS + w];
-    __syncthreads();
-  }
+  for (int q = 0; q < kPer; ++q) my_row[q * kRowStep] = stage[q];
+  __syncthreads();
   SeriesCtx cx{hist_all[w], list_all[w], n_t};
   if (p0 + w < n_pix)
-    process_series<V, ST>(xa, p0 + w, s, n_t, n_sub, mode, med_in, sig_in, med_out, sig_out, z, flag_count, cx);
+    process_series<V, ST>(series + w * RS, p0 + w, s, n_t, n_sub, mode, med_in, sig_in, med_out, sig_out, z,
+                          flag_count, cx);
 }
 
 // ------------------------------------------------------------ launcher
