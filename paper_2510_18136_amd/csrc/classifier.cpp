@@ -66,6 +66,8 @@ struct nsfrb_classifier {
   float* d_h = nullptr;         // head input [n][64]: channel maxima, candidate-position features
   float* d_dh = nullptr;
   int* d_arg = nullptr;         // position of each channel's maximum [n][32]
+  uint32_t* d_pool_part = nullptr;  // per-chunk maximum keys of the pooling pass
+  float* d_hs = nullptr;        // head's per-sample backward record [n][66]
   float* d_logits = nullptr;
   float* d_prob = nullptr;
   float* d_loss = nullptr;
@@ -85,6 +87,7 @@ void release(nsfrb_classifier* c) {
   if (!c) return;
   hipSetDevice(c->device);
   void* bufs[] = {c->d_theta, c->d_m, c->d_v, c->d_grad, c->d_part, c->d_part_db, c->d_h, c->d_dh, (void*)c->d_arg,
+                  (void*)c->d_pool_part, c->d_hs,
                   c->d_logits, c->d_prob, c->d_loss, c->d_cut_desc, c->d_delays, (void*)c->d_cube_ptrs};
   for (void* b : bufs)
     if (b) hipFree(b);
@@ -125,7 +128,7 @@ nsfrb_status forward(nsfrb_classifier* c, const uint16_t* x, int n, hipStream_t 
     NSFRB_HIP_TRY(launch_conv_fwd(kLayerCin[l], in, c->d_wf[l], c->d_theta + kL.b[l], c->d_act[l], n, T, Y, st));
     in = c->d_act[l];
   }
-  NSFRB_HIP_TRY(launch_pool(c->d_act[3], n, T * Y * kX, centre_pos(c), c->d_h, c->d_arg, st));
+  NSFRB_HIP_TRY(launch_pool(c->d_act[3], n, T * Y * kX, centre_pos(c), c->d_pool_part, c->d_h, c->d_arg, st));
   return NSFRB_OK;
 }
 
@@ -165,6 +168,8 @@ extern "C" nsfrb_status nsfrb_classifier_create(const nsfrb_classifier_config* c
   NSFRB_HIP_TRY(dalloc(&c->d_h, N * 2 * kCh));
   NSFRB_HIP_TRY(dalloc(&c->d_dh, N * 2 * kCh));
   NSFRB_HIP_TRY(dalloc(&c->d_arg, N * kCh));
+  NSFRB_HIP_TRY(dalloc(&c->d_pool_part, N * pool_chunks((int)npos) * kCh));
+  NSFRB_HIP_TRY(dalloc(&c->d_hs, N * (2 * kCh + 2)));
   NSFRB_HIP_TRY(dalloc(&c->d_logits, N));
   NSFRB_HIP_TRY(dalloc(&c->d_prob, N));
   NSFRB_HIP_TRY(dalloc(&c->d_loss, 4));
@@ -246,7 +251,7 @@ extern "C" nsfrb_status nsfrb_classifier_train_step(nsfrb_classifier* c, const v
   const uint16_t* x = (const uint16_t*)d_cutouts;
   nsfrb_status s = forward(c, x, n, st);
   if (s != NSFRB_OK) return s;
-  NSFRB_HIP_TRY(launch_head(c->d_h, d_labels, n, c->d_theta + kL.head, c->d_grad + kL.head, c->d_dh, c->d_logits,
+  NSFRB_HIP_TRY(launch_head(c->d_h, d_labels, n, c->d_theta + kL.head, c->d_hs, c->d_grad + kL.head, c->d_dh, c->d_logits,
                             c->d_prob, c->d_loss, 1, st));
   NSFRB_HIP_TRY(launch_pool_backward(c->d_dh, c->d_arg, c->d_act[3], n, npos, centre_pos(c), c->d_dpre[0], st));
   int cur = 0;
@@ -285,7 +290,7 @@ extern "C" nsfrb_status nsfrb_classifier_infer(nsfrb_classifier* c, const void* 
   NSFRB_HIP_TRY(hipSetDevice(c->device));
   nsfrb_status s = forward(c, (const uint16_t*)d_cutouts, n, st);
   if (s != NSFRB_OK) return s;
-  NSFRB_HIP_TRY(launch_head(c->d_h, nullptr, n, c->d_theta + kL.head, nullptr, nullptr, c->d_logits, d_prob, nullptr,
+  NSFRB_HIP_TRY(launch_head(c->d_h, nullptr, n, c->d_theta + kL.head, nullptr, nullptr, nullptr, c->d_logits, d_prob, nullptr,
                             0, st));
   return NSFRB_OK;
 }

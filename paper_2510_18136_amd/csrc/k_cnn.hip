@@ -190,120 +190,181 @@ __global__ void k_reduce_items(const float* __restrict__ part, int n_items, int 
 // ------------------------------------------------------------------- head
 // h[n] = [m, q]: m[c] = max over positions of act[n][pos][c] (first position on
 // ties; its index goes to arg[n][c]), q[c] = act at the candidate's position.
-__global__ __launch_bounds__(256) void k_pool(const uint16_t* __restrict__ act, int npos, int centre,
-                                              float* __restrict__ h, int* __restrict__ arg) {
-  __shared__ float rv[8 * kCH];
-  __shared__ int ri[8 * kCH];
-  const int n = blockIdx.x;
-  const int c = threadIdx.x % kCH, part = threadIdx.x / kCH;          // 8 interleaved parts of the positions
-  const uint16_t* a = act + (size_t)n * npos * kCH + c;
-  float best = -1.f;                                                  // activations are >= 0
-  int bi = 0;
-  for (int p = part; p < npos; p += 8) {
-    const float v = bf2f(a[(size_t)p * kCH]);
-    if (v > best) { best = v; bi = p; }                               // increasing p: first maximum kept
+//
+// Pass 1: G workgroups per sample, each over one chunk of positions, reduce a
+// 32-bit key per channel, (value bits << 16) | (0xFFFF - offset in the chunk):
+// activations are >= 0, so their BF16 bits order like their values and the
+// larger key is the larger value, then the earlier position (a maximum, so the
+// result does not depend on the order of the reduction). Pass 2 takes, for each
+// (sample, channel), the first chunk that holds the largest value.
+constexpr int kPoolChunks = 64;
+constexpr int kPoolThreads = 256;
+
+__device__ __forceinline__ uint32_t pool_key(uint32_t bits16, int off) {
+  const uint32_t v = (bits16 & 0x8000u) ? 0u : bits16;               // -0 counts as 0
+  return (v << 16) | (uint32_t)(0xFFFF - off);
+}
+
+__global__ __launch_bounds__(kPoolThreads) void k_pool_partial(const uint16_t* __restrict__ act, int npos, int chunk,
+                                                               uint32_t* __restrict__ part) {
+  __shared__ uint32_t red[kPoolThreads / kWave][kCH];
+  const int n = blockIdx.y, g = blockIdx.x;
+  const int cg = threadIdx.x & 3, r = threadIdx.x >> 2;                // 8 channels (16 bytes) per thread
+  const int p0 = g * chunk, p1 = min(p0 + chunk, npos);
+  const uint4* a = reinterpret_cast<const uint4*>(act + (size_t)n * npos * kCH) + cg;
+  uint32_t k[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) k[q] = 0u;
+#pragma unroll 4
+  for (int p = p0 + r; p < p1; p += kPoolThreads / 4) {
+    const uint4 v = a[(size_t)p * 4];
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    const int off = p - p0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      k[2 * q] = max(k[2 * q], pool_key(w[q] & 0xFFFFu, off));
+      k[2 * q + 1] = max(k[2 * q + 1], pool_key(w[q] >> 16, off));
+    }
   }
-  rv[part * kCH + c] = best;
-  ri[part * kCH + c] = bi;
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int s = 4; s < kWave; s <<= 1) k[q] = max(k[q], (uint32_t)__shfl_xor((int)k[q], s));
+  const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  if (l < 4) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[wv][cg * 8 + q] = k[q];
+  }
   __syncthreads();
   if (threadIdx.x < kCH) {
-    float m = rv[c];
-    int mi = ri[c];
-    for (int k = 1; k < 8; ++k) {
-      const float v = rv[k * kCH + c];
-      const int i = ri[k * kCH + c];
-      if (v > m || (v == m && i < mi)) { m = v; mi = i; }
-    }
-    h[(size_t)n * 2 * kCH + c] = m;
-    h[(size_t)n * 2 * kCH + kCH + c] = bf2f(a[(size_t)centre * kCH]);
-    arg[(size_t)n * kCH + c] = mi;
+    uint32_t m = red[0][threadIdx.x];
+    for (int w = 1; w < kPoolThreads / kWave; ++w) m = max(m, red[w][threadIdx.x]);
+    part[((size_t)n * gridDim.x + g) * kCH + threadIdx.x] = m;
   }
 }
 
-// MLP head (64 -> 32 ReLU -> 1), BCE-with-logits loss and its backward pass for
-// a batch of n <= 1024. theta_head = [W1[32][64], c1[32], w2[32], c2[1]];
-// gradients are written in the same order.
+__global__ void k_pool_finish(const uint32_t* __restrict__ part, int n_chunks, int chunk, const uint16_t* __restrict__ act,
+                              int N, int npos, int centre, float* __restrict__ h, int* __restrict__ arg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N * kCH) return;
+  const int n = i / kCH, c = i % kCH;
+  uint32_t best = part[(size_t)n * n_chunks * kCH + c];
+  int g_best = 0;
+  for (int g = 1; g < n_chunks; ++g) {
+    const uint32_t k = part[((size_t)n * n_chunks + g) * kCH + c];
+    if ((k >> 16) > (best >> 16)) { best = k; g_best = g; }            // strictly larger: earlier chunk kept on ties
+  }
+  h[(size_t)n * 2 * kCH + c] = bf2f((uint16_t)(best >> 16));
+  h[(size_t)n * 2 * kCH + kCH + c] = bf2f(act[((size_t)n * npos + centre) * kCH + c]);
+  arg[i] = g_best * chunk + (0xFFFF - (int)(best & 0xFFFFu));
+}
+
+// MLP head (64 -> 32 ReLU -> 1) and BCE-with-logits loss for a batch of n.
+// theta_head = [W1[32][64], c1[32], w2[32], c2[1]]; gradients use the same order.
+// k_head_sample: one wave per sample (lane l: hidden unit l % 32, half l / 32 of
+// the inputs): logit, probability and, when training, the sample's loss, its
+// gradient dz, d(loss)/du, relu(u) (into hs[i][66]) and d(loss)/dh.
+// k_head_grad: one thread per head parameter sums the samples in index order.
 constexpr int kH = 2 * kCH;
-__global__ __launch_bounds__(256) void k_head(const float* __restrict__ h, const float* __restrict__ labels, int n,
-                                              const float* __restrict__ th, float* __restrict__ gh,
-                                              float* __restrict__ dh, float* __restrict__ logits,
-                                              float* __restrict__ prob, float* __restrict__ loss_out, int backward) {
-  __shared__ float W1[kCH * kH], c1[kCH], w2[kCH];
-  __shared__ float gW1[kCH * kH], gc1[kCH], gw2[kCH], gc2, lsum;
-  for (int i = threadIdx.x; i < kCH * kH; i += blockDim.x) { W1[i] = th[i]; gW1[i] = 0.f; }
-  if (threadIdx.x < kCH) {
-    c1[threadIdx.x] = th[kCH * kH + threadIdx.x];
-    w2[threadIdx.x] = th[kCH * kH + kCH + threadIdx.x];
-    gc1[threadIdx.x] = 0.f;
-    gw2[threadIdx.x] = 0.f;
-  }
-  if (threadIdx.x == 0) { gc2 = 0.f; lsum = 0.f; }
-  __syncthreads();
-  const float c2 = th[kCH * kH + 2 * kCH];
-  // one thread per sample: forward, loss, backward into per-sample dh; weight
-  // gradients summed with atomics in LDS (float adds of one batch)
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const float* hv = h + (size_t)i * kH;
-    float u[kCH];
-    float z = c2;
-    for (int j = 0; j < kCH; ++j) {
-      float s = c1[j];
-      for (int c = 0; c < kH; ++c) s += W1[j * kH + c] * hv[c];
-      u[j] = s;
-      z += w2[j] * fmaxf(s, 0.f);
-    }
+constexpr int kHS = 2 * kCH + 2;          // per-sample record: du[32], relu(u)[32], dz, loss
+constexpr int kHeadParams = kCH * kH + 2 * kCH + 1;
+
+__global__ __launch_bounds__(256) void k_head_sample(const float* __restrict__ h, const float* __restrict__ labels,
+                                                     int n, const float* __restrict__ th, float* __restrict__ hs,
+                                                     float* __restrict__ dh, float* __restrict__ logits,
+                                                     float* __restrict__ prob, int backward) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (i >= n) return;                                                  // whole waves leave together
+  const int l = threadIdx.x % kWave, j = l % kCH, hf = l / kCH;
+  const float* hv = h + (size_t)i * kH + hf * kCH;
+  const float* wr = th + j * kH + hf * kCH;
+  float s = 0.f;
+#pragma unroll 8
+  for (int c = 0; c < kCH; ++c) s += wr[c] * hv[c];
+  s += __shfl_xor(s, kCH);
+  const float u = s + th[kCH * kH + j];
+  const float ru = fmaxf(u, 0.f);
+  const float w2 = th[kCH * kH + kCH + j];
+  float t = hf == 0 ? w2 * ru : 0.f;
+#pragma unroll
+  for (int k = 1; k < kWave; k <<= 1) t += __shfl_xor(t, k);          // same sum in every lane
+  const float z = th[kCH * kH + 2 * kCH] + t;
+  const float p = 1.0f / (1.0f + expf(-z));
+  if (l == 0) {
     logits[i] = z;
-    prob[i] = 1.0f / (1.0f + expf(-z));
-    if (backward) {
-      const float yv = labels[i];
-      const float li = fmaxf(z, 0.f) - z * yv + log1pf(expf(-fabsf(z)));
-      atomicAdd(&lsum, li / (float)n);
-      const float dz = (1.0f / (1.0f + expf(-z)) - yv) / (float)n;
-      atomicAdd(&gc2, dz);
-      for (int j = 0; j < kCH; ++j) {
-        atomicAdd(&gw2[j], dz * fmaxf(u[j], 0.f));
-        u[j] = u[j] > 0.f ? dz * w2[j] : 0.f;                         // u now holds d(loss)/du
-        if (u[j] != 0.f) {
-          atomicAdd(&gc1[j], u[j]);
-          for (int c = 0; c < kH; ++c) atomicAdd(&gW1[j * kH + c], u[j] * hv[c]);
-        }
-      }
-      for (int c = 0; c < kH; ++c) {
-        float d = 0.f;
-        for (int j = 0; j < kCH; ++j) d += u[j] * W1[j * kH + c];
-        dh[(size_t)i * kH + c] = d;
-      }
-    }
+    prob[i] = p;
   }
-  __syncthreads();
-  if (backward) {
-    for (int i = threadIdx.x; i < kCH * kH; i += blockDim.x) gh[i] = gW1[i];
-    if (threadIdx.x < kCH) {
-      gh[kCH * kH + threadIdx.x] = gc1[threadIdx.x];
-      gh[kCH * kH + kCH + threadIdx.x] = gw2[threadIdx.x];
-    }
-    if (threadIdx.x == 0) {
-      gh[kCH * kH + 2 * kCH] = gc2;
-      loss_out[0] = lsum;
-    }
+  if (!backward) return;
+  const float yv = labels[i];
+  const float dz = (p - yv) / (float)n;
+  const float du = u > 0.f ? dz * w2 : 0.f;
+  float* rec = hs + (size_t)i * kHS;
+  rec[l] = hf == 0 ? du : ru;
+  if (l == 0) {
+    rec[2 * kCH] = dz;
+    rec[2 * kCH + 1] = fmaxf(z, 0.f) - z * yv + log1pf(expf(-fabsf(z)));
   }
+  float d = 0.f;
+  for (int k = 0; k < kCH; ++k) d += __shfl(du, k) * th[k * kH + l];
+  dh[(size_t)i * kH + l] = d;
+}
+
+__global__ void k_head_grad(const float* __restrict__ h, const float* __restrict__ hs, int n, float* __restrict__ gh,
+                            float* __restrict__ loss_out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > kHeadParams) return;
+  float s = 0.f;
+  if (p < kCH * kH) {                                                  // W1[j][c]: du_j * h_c
+    const int j = p / kH, c = p % kH;
+    for (int i = 0; i < n; ++i) s += hs[(size_t)i * kHS + j] * h[(size_t)i * kH + c];
+  } else if (p < kCH * kH + kCH) {                                     // c1[j]: du_j
+    const int j = p - kCH * kH;
+    for (int i = 0; i < n; ++i) s += hs[(size_t)i * kHS + j];
+  } else if (p < kCH * kH + 2 * kCH) {                                 // w2[j]: dz * relu(u_j)
+    const int j = p - kCH * kH - kCH;
+    for (int i = 0; i < n; ++i) s += hs[(size_t)i * kHS + 2 * kCH] * hs[(size_t)i * kHS + kCH + j];
+  } else if (p == kHeadParams - 1) {                                   // c2: dz
+    for (int i = 0; i < n; ++i) s += hs[(size_t)i * kHS + 2 * kCH];
+  } else {                                                             // mean loss
+    for (int i = 0; i < n; ++i) s += hs[(size_t)i * kHS + 2 * kCH + 1];
+    loss_out[0] = s / (float)n;
+    return;
+  }
+  gh[p] = s;
 }
 
 // dpre4[n][pos][c] = bf16(g * (act4[n][pos][c] > 0)) with g = dm[n][c] at the
-// channel's maximum, + dq[n][c] at the candidate position, 0 elsewhere.
+// channel's maximum, + dq[n][c] at the candidate position, 0 elsewhere; eight
+// channels (16 bytes) per thread.
 __global__ void k_pool_backward(const float* __restrict__ dh, const int* __restrict__ arg,
-                                const uint16_t* __restrict__ act, int npos, int centre, long long total,
+                                const uint16_t* __restrict__ act, int npos, int centre, long long total8,
                                 uint16_t* __restrict__ dpre) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total8;
        i += (long long)gridDim.x * blockDim.x) {
-    const int c = (int)(i % kCH);
-    const long long r = i / kCH;
+    const int cg = (int)(i & 3);
+    const long long r = i >> 2;
     const int pos = (int)(r % npos);
     const long long n = r / npos;
-    float g = 0.f;
-    if (pos == arg[n * kCH + c]) g = dh[n * kH + c];
-    if (pos == centre) g += dh[n * kH + kCH + c];
-    dpre[i] = f2bf(bf2f(act[i]) > 0.f ? g : 0.f);
+    const uint4 av = reinterpret_cast<const uint4*>(act)[i];
+    const uint32_t aw[4] = {av.x, av.y, av.z, av.w};
+    const int* ar = arg + n * kCH + cg * 8;
+    const float* dm = dh + n * kH + cg * 8;
+    uint32_t ow[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t o = 0;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int c = 2 * q + e;
+        float g = 0.f;
+        if (pos == ar[c]) g = dm[c];
+        if (pos == centre) g += dm[kCH + c];
+        const uint16_t ab = (uint16_t)(aw[q] >> (16 * e));
+        o |= (uint32_t)f2bf(bf2f(ab) > 0.f ? g : 0.f) << (16 * e);
+      }
+      ow[q] = o;
+    }
+    reinterpret_cast<uint4*>(dpre)[i] = make_uint4(ow[0], ow[1], ow[2], ow[3]);
   }
 }
 
@@ -396,22 +457,32 @@ hipError_t launch_conv_wgrad(int cin, const uint16_t* x, const uint16_t* dpre, f
   return hipGetLastError();
 }
 
-hipError_t launch_pool(const uint16_t* act, int N, int npos, int centre, float* h, int* arg, hipStream_t st) {
-  hipLaunchKernelGGL(k_pool, dim3(N), dim3(256), 0, st, act, npos, centre, h, arg);
+int pool_chunks(int npos) { return std::max(1, std::min(kPoolChunks, (npos + 1023) / 1024)); }
+
+hipError_t launch_pool(const uint16_t* act, int N, int npos, int centre, uint32_t* part, float* h, int* arg,
+                       hipStream_t st) {
+  const int G = pool_chunks(npos), chunk = (npos + G - 1) / G;
+  if (chunk > 0x10000) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pool_partial, dim3(G, N), dim3(kPoolThreads), 0, st, act, npos, chunk, part);
+  hipLaunchKernelGGL(k_pool_finish, dim3((N * kCH + 255) / 256), dim3(256), 0, st, part, G, chunk, act, N, npos,
+                     centre, h, arg);
   return hipGetLastError();
 }
 
-hipError_t launch_head(const float* h, const float* labels, int n, const float* th, float* gh, float* dh, float* logits,
-                       float* prob, float* loss, int backward, hipStream_t st) {
-  hipLaunchKernelGGL(k_head, dim3(1), dim3(256), 0, st, h, labels, n, th, gh, dh, logits, prob, loss, backward);
+hipError_t launch_head(const float* h, const float* labels, int n, const float* th, float* hs, float* gh, float* dh,
+                       float* logits, float* prob, float* loss, int backward, hipStream_t st) {
+  hipLaunchKernelGGL(k_head_sample, dim3((n + 3) / 4), dim3(256), 0, st, h, labels, n, th, hs, dh, logits, prob,
+                     backward);
+  if (backward)
+    hipLaunchKernelGGL(k_head_grad, dim3((kHeadParams + 1 + 255) / 256), dim3(256), 0, st, h, hs, n, gh, loss);
   return hipGetLastError();
 }
 
 hipError_t launch_pool_backward(const float* dh, const int* arg, const uint16_t* act, int N, int npos, int centre,
                                 uint16_t* dpre, hipStream_t st) {
-  const long long total = (long long)N * npos * kCH;
-  const unsigned grid = (unsigned)std::min<long long>((total + 255) / 256, 65536LL * 4);
-  hipLaunchKernelGGL(k_pool_backward, dim3(grid), dim3(256), 0, st, dh, arg, act, npos, centre, total, dpre);
+  const long long total8 = (long long)N * npos * (kCH / 8);
+  const unsigned grid = (unsigned)std::min<long long>((total8 + 255) / 256, 65536LL);
+  hipLaunchKernelGGL(k_pool_backward, dim3(grid), dim3(256), 0, st, dh, arg, act, npos, centre, total8, dpre);
   return hipGetLastError();
 }
 

@@ -83,9 +83,12 @@ hipError_t launch_conv_bwd_data(const uint16_t* dpre, const uint16_t* wb, const 
 int wgrad_items(int N, int T);
 hipError_t launch_conv_wgrad(int cin, const uint16_t* x, const uint16_t* dpre, float* part, float* part_db, float* dw,
                              float* db, int N, int T, int Y, hipStream_t st);
-hipError_t launch_pool(const uint16_t* act, int N, int npos, int centre, float* h, int* arg, hipStream_t st);
-hipError_t launch_head(const float* h, const float* labels, int n, const float* th, float* gh, float* dh, float* logits,
-                       float* prob, float* loss, int backward, hipStream_t st);
+int pool_chunks(int npos);   // partial keys per sample written by launch_pool (part holds N * this * 32)
+hipError_t launch_pool(const uint16_t* act, int N, int npos, int centre, uint32_t* part, float* h, int* arg,
+                       hipStream_t st);
+// hs: per-sample scratch of 66 floats (training only)
+hipError_t launch_head(const float* h, const float* labels, int n, const float* th, float* hs, float* gh, float* dh,
+                       float* logits, float* prob, float* loss, int backward, hipStream_t st);
 hipError_t launch_pool_backward(const float* dh, const int* arg, const uint16_t* act, int N, int npos, int centre,
                                 uint16_t* dpre, hipStream_t st);
 hipError_t launch_adam(float* th, float* m, float* v, const float* g, int n, float lr, float b1, float b2, float eps,

@@ -1,7 +1,8 @@
 """GPU tests of the candidate classifier (needs an MI355X).
 
 * gradients of one BF16 MFMA training step against the FP64 oracle with the
-  same BF16 rounding points, per parameter tensor (reduced cutouts: 4 x 4 x 32);
+  same BF16 rounding points, per parameter tensor (reduced cutouts, t x y x 32
+  with t x y from 4 x 4 to 40 x 8);
 * the first Adam step against its closed form;
 * inference probabilities against the oracle's sigmoid(logit);
 * cutout extraction against its definition written out in NumPy;
@@ -49,15 +50,17 @@ def tensor_slices():
     return [(nm, slice(starts[i], starts[i + 1])) for i, nm in enumerate(names)]
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_gradients_match_oracle(seed):
-    x, theta, labels = make_case(seed)
+# the larger cutouts split the pooling pass over several position chunks (the
+# last one ragged): 4 x 4 -> one chunk, 16 x 8 -> 4, 13 x 5 -> 3 uneven, 40 x 8 -> 10
+@pytest.mark.parametrize("seed,n,T,Y", [(0, 3, 4, 4), (1, 3, 4, 4), (2, 2, 16, 8), (6, 2, 13, 5), (7, 1, 40, 8)])
+def test_gradients_match_oracle(seed, n, T, Y):
+    x, theta, labels = make_case(seed, n=n, T=T, Y=Y)
     n, T, Y = x.shape[:3]
     with nsfrb.Classifier(max_batch=n, n_time=T, ny=Y, lr=0.0) as c:
         c.set_params(theta)
         xd = bf16_device(x)
         yd = torch.from_numpy(labels.astype(np.float32)).cuda()
-        print(f"[gpu] classifier grad check seed={seed}", flush=True)
+        print(f"[gpu] classifier grad check seed={seed} n={n} T={T} Y={Y}", flush=True)
         loss = c.train_step(xd.data_ptr(), yd.data_ptr(), n, update=False,
                             stream=torch.cuda.current_stream().cuda_stream)
         g = c.grads().astype(np.float64)
