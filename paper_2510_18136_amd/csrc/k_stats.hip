@@ -24,9 +24,14 @@
 //
 // The median selects over the FP32 samples themselves. The MAD selects over
 // the FP32 roundings of the FP64 distances |x - median|: rounding is monotone,
-// so the k-th smallest FP64 distance is among the samples whose rounded
-// distance equals the k-th smallest rounded distance, and its rank among them
-// is known; those few candidates are compared in FP64.
+// so all samples of a lower key bin have smaller FP64 distances than those of
+// the bin holding the wanted rank, and all samples of a higher bin larger ones.
+// When that bin has <= 64 members, the FP64 values of its members are gathered
+// and sorted across the wave, which yields both middle order statistics at
+// once. The median's key range comes from the finite-check pass; the MAD's is
+// [0, largest distance], the largest distance being that of the series' minimum
+// or maximum. Ranges that cannot be binned that far (long runs of equal keys)
+// take a general path: the k-th key, then the FP64 values among its ties.
 //
 // Normalisation divides in FP64 by Markstein's method: with r = RN(1/sigma)
 // (a correctly rounded division, once per series), q0 = RN(a*r),
@@ -185,6 +190,103 @@ __device__ __forceinline__ Sel select_kth_f32(const Key& key, int k, const Serie
   }
 }
 
+// Exact FP64 order statistics k and (if want_second) k + 1 of val(j), where the
+// FP32 keys key(j) = RN32(val(j)) all lie in [lo, hi]. Rounding is monotone, so
+// every sample of a lower key bin has a smaller value than every sample of the
+// bin holding rank k, and every sample of a higher bin a larger one: once that
+// bin has <= 64 members, their FP64 values sorted across the wave give the
+// answer directly. Returns false (nothing decided) when the range cannot be
+// binned down to such a bin; the caller then takes the general path.
+template <int V, class Key, class Val>
+__device__ __forceinline__ bool select_values(const Key& key, const Val& val, int k, bool want_second, float lo,
+                                              float hi, const SeriesCtx& cx, double& first, double& second) {
+  const int l = lane_id();
+  int krem = k;                                    // rank among keys in [lo, hi]
+  for (int iter = 0; iter < 48; ++iter) {
+    if (!(lo < hi)) return false;
+    const float scale = 256.0f / (hi - lo);
+    if (!(scale > 0.0f && scale < 1e30f)) return false;
+    cx.hist[4 * l + 0] = 0; cx.hist[4 * l + 1] = 0; cx.hist[4 * l + 2] = 0; cx.hist[4 * l + 3] = 0;
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const float v = key(j);
+      if (v >= lo && v <= hi) {
+        int b = (int)((v - lo) * scale);
+        b = b > 255 ? 255 : b;
+        atomicAdd(&cx.hist[b], 1u);
+      }
+    }
+    wave_lds_sync();
+    const uint32_t h0 = cx.hist[4 * l], h1 = cx.hist[4 * l + 1], h2 = cx.hist[4 * l + 2], h3 = cx.hist[4 * l + 3];
+    const uint32_t s4 = h0 + h1 + h2 + h3;
+    const uint32_t incl = wave_incl_scan(s4);
+    const uint32_t excl = incl - s4;
+    const uint64_t m = ballot((excl <= (uint32_t)krem) && ((uint32_t)krem < incl));
+    const int L = __ffsll((long long)m) - 1;
+    const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)excl, L);
+    const uint32_t a0 = (uint32_t)__builtin_amdgcn_readlane((int)h0, L), a1 = (uint32_t)__builtin_amdgcn_readlane((int)h1, L);
+    const uint32_t a2 = (uint32_t)__builtin_amdgcn_readlane((int)h2, L), a3 = (uint32_t)__builtin_amdgcn_readlane((int)h3, L);
+    const uint32_t r = (uint32_t)krem - e;
+    int bsel;
+    uint32_t before, cnt;
+    if (r < a0) { bsel = 0; before = 0; cnt = a0; }
+    else if (r < a0 + a1) { bsel = 1; before = a0; cnt = a1; }
+    else if (r < a0 + a1 + a2) { bsel = 2; before = a0 + a1; cnt = a2; }
+    else { bsel = 3; before = a0 + a1 + a2; cnt = a3; }
+    const int B = 4 * L + bsel;
+    krem = (int)(r - before);
+    if (cnt <= 64) {
+      int base = 0;
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const float v = key(j);
+        bool mem = false;
+        if (v >= lo && v <= hi) {
+          int b = (int)((v - lo) * scale);
+          b = b > 255 ? 255 : b;
+          mem = (b == B);
+        }
+        const uint64_t mm = ballot(mem);
+        if (mem) cx.list[base + lanes_below(mm)] = val(j);
+        base += popc64(mm);
+      }
+      wave_lds_sync();
+      double c = (l < (int)cnt) ? cx.list[l] : __builtin_inf();
+      wave_lds_sync();
+      c = wave_sort_asc(c);
+      first = readlane_d(c, krem);
+      if (!want_second) return true;
+      if (krem + 1 < (int)cnt) {
+        second = readlane_d(c, krem + 1);
+        return true;
+      }
+      // rank k is the bin's largest value: rank k + 1 is the smallest value above it
+      double nx = __builtin_inf();
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const double v = val(j);
+        if (v > first) nx = fmin(nx, v);
+      }
+      second = wave_min(nx);
+      return true;
+    }
+    float nlo = __builtin_inff(), nhi = -__builtin_inff();
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const float v = key(j);
+      if (v >= lo && v <= hi) {
+        int b = (int)((v - lo) * scale);
+        b = b > 255 ? 255 : b;
+        if (b == B) { nlo = fminf(nlo, v); nhi = fmaxf(nhi, v); }
+      }
+    }
+    lo = wave_min_f(nlo);
+    hi = wave_max_f(nhi);
+  }
+  return false;
+}
+
 // The (rank)-th and (rank+1)-th smallest FP64 values val(j) among the samples
 // whose key equals kv; `second` is +inf when there is no (rank+1)-th tie.
 template <int V, class Key, class Val>
@@ -298,9 +400,14 @@ __device__ __forceinline__ void process_series(const float* xs, int p, int s, in
   const int l = lane_id();
   const LdsSeries x{xs, l};
   bool bad = false;
+  float xmin = __builtin_inff(), xmax = -__builtin_inff();   // NaN padding is ignored by fminf/fmaxf
 #pragma unroll
-  for (int j = 0; j < V; ++j)
-    if (64 * j + l < n_t && !__builtin_isfinite(x(j))) bad = true;
+  for (int j = 0; j < V; ++j) {
+    const float v = x(j);
+    if (64 * j + l < n_t && !__builtin_isfinite(v)) bad = true;
+    xmin = fminf(xmin, v);
+    xmax = fmaxf(xmax, v);
+  }
   const bool any_bad = ballot(bad) != 0;
 
   long long nflag = 0;
@@ -310,15 +417,31 @@ __device__ __forceinline__ void process_series(const float* xs, int p, int s, in
     if (any_bad) {
       med = __builtin_nan(""); sig = __builtin_nan(""); usable = false;
     } else {
+      xmin = wave_min_f(xmin);
+      xmax = wave_max_f(xmax);
+      const int k1 = (n_t - 1) / 2;
+      const bool even = (n_t & 1) == 0;
+      double a = 0.0, b = 0.0;
       auto vx = [&](int j) { return (double)x(j); };
-      med = median_via_keys<true, V>(x, vx, cx);
+      if (select_values<V>(x, vx, k1, even, xmin, xmax, cx, a, b))
+        med = even ? (a + b) * 0.5 : a;
+      else
+        med = median_via_keys<true, V>(x, vx, cx);
       // separate copies of the median for each use, so the compiler recomputes the
       // FP64 differences instead of keeping all of them live
       double mk = med, mv = med;
       asm volatile("" : "+v"(mk));
       asm volatile("" : "+v"(mv));
       auto vd = [&](int j) { return fabs((double)x(j) - mv); };
-      const double mad = median_via_keys<false, V>(DistKeys{x, mk}, vd, cx);
+      // distance keys lie in [0, RN32(largest distance)], the largest distance
+      // being that of the series' minimum or maximum (the map is monotone on
+      // each side of the median)
+      const float dhi = fmaxf((float)fabs((double)xmax - med), (float)fabs((double)xmin - med));
+      double mad;
+      if (select_values<V>(DistKeys{x, mk}, vd, k1, even, 0.0f, dhi, cx, a, b))
+        mad = even ? (a + b) * 0.5 : a;
+      else
+        mad = median_via_keys<false, V>(DistKeys{x, mk}, vd, cx);
       sig = kMadToSigma * mad;
       usable = (sig > 0.0) && (sig < __builtin_inf());
     }

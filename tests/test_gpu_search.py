@@ -202,6 +202,31 @@ def test_integer_ties_first_time_and_smallest_trial():
     assert (g["best_d"] == 0).all() and (g["best_w"] == 2).all()
 
 
+# Noise statistics on 1024 series per case, compared bit for bit: Gaussian
+# series (the selection bin holding the middle rank is small; about one series
+# in twenty has that rank at the bin's top, so the next value comes from a scan),
+# odd lengths (one middle value), integer and 1/8-grid values (long runs of equal
+# keys: the general tie path), and series with a wide bright pulse (skewed range).
+@pytest.mark.parametrize("kind,nt", [("gauss", 2048), ("gauss", 2047), ("int", 2048), ("int", 300),
+                                     ("coarse", 2048), ("coarse", 1000), ("pulse", 2048), ("pulse", 513)])
+def test_noise_stats_exact(kind, nt):
+    rng = np.random.default_rng(10 * nt + ["gauss", "int", "coarse", "pulse"].index(kind))
+    nx, ny, ns = 16, 8, 8
+    shape = (nt, ns, nx * ny)
+    if kind == "int":
+        cube = rng.integers(-6, 7, size=shape).astype(np.float32)
+    elif kind == "coarse":
+        cube = (np.round(rng.standard_normal(shape) * 8) / 8).astype(np.float32)
+    else:
+        cube = (rng.standard_normal(shape) * 1.3 + 0.2).astype(np.float32)
+        if kind == "pulse":
+            t0 = int(rng.integers(0, nt // 2))
+            cube[t0:t0 + nt // 3] += np.float32(20.0)
+    cfg = nsfrb.SearchConfig(nx, ny, nt, np.linspace(1.311, 1.499, ns), [0.0, 500.0], [1, 3], snr_threshold=50.0)
+    g, o = run_gpu(cube, cfg), oracle_run(cube, cfg)
+    compare(g, o, cfg)
+
+
 def test_no_valid_window_and_invalid_trials():
     nt, ns = 20, 4
     rng = np.random.default_rng(3)
