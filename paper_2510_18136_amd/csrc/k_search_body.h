@@ -29,7 +29,9 @@
 //    binary digits placed end to end. Each output is a balanced sum, so the
 //    FP32 error grows with log2(w) rather than w;
 //  * a window shifted by k samples is read from register (c+k) mod C of lane
-//    l + (c+k)/C: the same lane, a DPP wave shift by one lane, or ds_bpermute.
+//    l + (c+k)/C: the same lane, one or two DPP wave shifts by one lane (two
+//    VALU moves return sooner than one ds_bpermute round trip through the LDS
+//    pipeline), or ds_bpermute.
 
 #ifndef NSFRB_RTC_PROLOGUE
 #error "compile through the search plan: the prologue defines ST, NSFRB_NW and the shape classes"
@@ -64,6 +66,7 @@ __device__ __forceinline__ void shift_add(float (&out)[C], const float (&a)[C], 
     float v;
     if (q == 0) v = b[r];
     else if (q == 1) v = lane_next(b[r]);
+    else if (q == 2) v = lane_next(lane_next(b[r]));
     else v = lane_ahead(b[r], q, l);
     out[c] = a[c] + v;
   }
