@@ -57,8 +57,8 @@ struct nsfrb_classifier {
   float* d_m = nullptr;
   float* d_v = nullptr;
   float* d_grad = nullptr;
-  uint16_t* d_wf[4] = {};      // BF16 forward weights [co][tap][ci]
-  uint16_t* d_wb[4] = {};      // BF16 backward-data weights [ci][26 - tap][co] (layers 2..4)
+  uint16_t* d_wf[4] = {};      // BF16 forward weights in convolution-operand order
+  uint16_t* d_wb[4] = {};      // BF16 backward-data weights (flipped taps, transposed channels; layers 2..4)
   uint16_t* d_act[4] = {};     // conv outputs a_1..a_4 [n][t][y][x][32]
   uint16_t* d_dpre[2] = {};    // pre-activation gradients (ping-pong)
   float* d_part = nullptr;

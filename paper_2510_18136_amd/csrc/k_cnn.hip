@@ -9,16 +9,16 @@
 // ReLU; head input = every channel's global maximum and its value at the
 // candidate's position (64 features); 64->32 ReLU, 32->1 logit.
 //
-// Tensors are channels-last BF16; accumulation is FP32 on the matrix cores
-// (v_mfma_f32_32x32x8_bf16: D[32x32] += A[32x8] * B[8x32]; lane l holds
-// A[l%32][4(l/32)..+3], B[4(l/32)..+3][l%32], D[8(r/4)+4(l/32)+r%4][l%32]).
+// Tensors are channels-last BF16; accumulation is FP32 on the matrix cores.
 //  * convolution (forward, and backward-data with transposed, flipped
-//    weights): one wave per output row (n, t, y): M = 32 output channels,
-//    N = the 32 x positions, K = 27 taps x input channels; weights in LDS;
-//  * weight gradient: M = 32 output channels, N = input channels, K =
-//    positions; each output row's pre-activation gradient (transposed) and
-//    the nine input rows of its taps are staged in LDS; each workgroup writes
-//    its partial sums, which a second kernel adds in a fixed order.
+//    weights): implicit GEMM on v_mfma_f32_32x32x16_bf16 with the weights and a
+//    ring of input planes in LDS (see k_conv3);
+//  * weight gradient (v_mfma_f32_32x32x8_bf16: lane l holds A[l%32][4(l/32)..+3],
+//    B[4(l/32)..+3][l%32], D[8(r/4)+4(l/32)+r%4][l%32]): M = 32 output
+//    channels, N = input channels, K = positions; each output row's
+//    pre-activation gradient (transposed) and the nine input rows of its taps
+//    are staged in LDS; each workgroup writes its partial sums, which a second
+//    kernel adds in a fixed order.
 #include <algorithm>
 
 #include "device_common.h"
@@ -27,6 +27,7 @@
 namespace nsfrb {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kCH = 32;       // hidden channels (conv outputs)
@@ -38,57 +39,139 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint
 
 // ------------------------------------------------------------ convolution
 // MODE 0: out = bf16(relu(conv + bias)).   MODE 1: out = bf16(conv * (mask > 0)).
+//
+// Implicit GEMM on v_mfma_f32_32x32x16_bf16 (D[32x32] += A[32x16] * B[16x32];
+// lane l holds A[l%32][8(l/32)..+7] and B[8(l/32)..+7][l%32] as eight BF16, and
+// D as for the 32x32x8 form). Per output row (n, t, y): M = 32 output channels,
+// N = the 32 x positions, K = 27 taps x CIN input channels in steps of 16.
+// A workgroup of 8 waves takes (n, 8 consecutive y, up to kConvTT consecutive
+// t); wave w computes row y0 + w of each plane in turn. The weights sit in LDS
+// in operand order (step s, lane l: 16 bytes), so each A operand is one
+// conflict-free 16-byte read. Input planes t-1, t, t+1 (rows y0-1 .. y0+8, a
+// zero halo in x) live in a 4-slot ring; the loads of plane t+2 are issued
+// before the matrix work of plane t and stored into the free slot after it. In
+// a staged row the 16-byte channel chunk c of position xs sits at chunk
+// c ^ swz(xs), so the 32 lanes of a B read hit distinct banks.
+constexpr int kConvWaves = 8;
+constexpr int kConvYT = kConvWaves;       // output rows (y) per plane per workgroup
+constexpr int kConvRY = kConvYT + 2;      // staged rows per plane (y halo)
+constexpr int kConvXS = kXW + 2;          // staged positions per row (x halo)
+constexpr int kConvTT = 16;               // planes per workgroup
+
+template <int CIN>
+__device__ __forceinline__ int conv_swz(int xs) {
+  constexpr int G8 = CIN / 8;             // 16-byte chunks per position
+  return (xs / (8 / G8)) & (G8 - 1);
+}
+
 template <int CIN, int MODE>
-__global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
-                                               const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-                                               uint16_t* __restrict__ out, int N, int T, int Y) {
-  __shared__ __attribute__((aligned(16))) uint16_t wl[kCH * kTaps * CIN];
-  for (int i = threadIdx.x; i < kCH * kTaps * CIN / 4; i += blockDim.x)
-    reinterpret_cast<uint2*>(wl)[i] = reinterpret_cast<const uint2*>(w)[i];
-  __syncthreads();
-  const long long rows = (long long)N * T * Y;
-  const long long row = (long long)blockIdx.x * 4 + threadIdx.x / 64;
-  if (row >= rows) return;                                   // no barrier below
-  const int l = lane_id();
-  const int n = (int)(row / ((long long)T * Y));
-  const int t = (int)((row / Y) % T);
-  const int y = (int)(row % Y);
-  const int x = l & 31, kq = l >> 5, co = l & 31;
-  v16f acc = {};
-#pragma unroll 1
-  for (int tap = 0; tap < kTaps; ++tap) {
-    const int kt = tap / 9, ky = (tap / 3) % 3, kx = tap % 3;
-    const int tt = t + kt - 1, yy = y + ky - 1, xx = x + kx - 1;
-    const bool ok = tt >= 0 && tt < T && yy >= 0 && yy < Y && xx >= 0 && xx < kXW;
-    const uint16_t* src = in + ((((size_t)n * T + (ok ? tt : 0)) * Y + (ok ? yy : 0)) * kXW + (ok ? xx : 0)) * CIN;
-#pragma unroll
-    for (int k8 = 0; k8 < CIN / 8; ++k8) {
-      const int ci = k8 * 8 + kq * 4;
-      const v4s a = *reinterpret_cast<const v4s*>(&wl[(co * kTaps + tap) * CIN + ci]);
-      v4s b = {0, 0, 0, 0};
-      if (ok) b = *reinterpret_cast<const v4s*>(src + ci);
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-    }
+__global__ __launch_bounds__(kConvWaves * kWave) void k_conv3(const uint16_t* __restrict__ in,
+                                                              const uint16_t* __restrict__ wm,
+                                                              const float* __restrict__ bias,
+                                                              const uint16_t* __restrict__ mask,
+                                                              uint16_t* __restrict__ out, int N, int T, int Y) {
+  constexpr int G8 = CIN / 8;
+  constexpr int S = kTaps * CIN / 16;                    // K steps
+  constexpr int ROW = kConvXS * G8;                      // 16-byte chunks per staged row
+  constexpr int SLOT = kConvRY * ROW;
+  constexpr int PLANE = kConvRY * kXW * G8;              // chunks loaded per plane
+  constexpr int NT = kConvWaves * kWave;
+  constexpr int PER = (PLANE + NT - 1) / NT;
+  __shared__ uint4 wl[S * kWave];
+  __shared__ uint4 xl[4 * SLOT];
+
+  const int n_yb = (Y + kConvYT - 1) / kConvYT, n_tb = (T + kConvTT - 1) / kConvTT;
+  const int blk = blockIdx.x;
+  const int tb = blk % n_tb, yb = (blk / n_tb) % n_yb, n = blk / (n_tb * n_yb);
+  const int y0 = yb * kConvYT, t0 = tb * kConvTT, t1 = min(t0 + kConvTT, T);
+  const int tid = threadIdx.x, l = lane_id();
+  const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+
+  for (int i = tid; i < S * kWave; i += NT) wl[i] = reinterpret_cast<const uint4*>(wm)[i];
+  for (int i = tid; i < 4 * kConvRY * 2 * G8; i += NT) {           // x halo of every slot and row
+    const int c = i % G8, side = (i / G8) % 2, r = i / (2 * G8);
+    xl[r * ROW + (side ? kConvXS - 1 : 0) * G8 + c] = make_uint4(0u, 0u, 0u, 0u);
   }
-  const size_t pos = (((size_t)n * T + t) * Y + y) * kXW + x;
+  // plane tp -> registers (zero outside the cube)
+  auto fetch = [&](int tp, uint4 (&v)[PER]) {
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    const int c0 = 8 * g + 4 * kq;
-    uint16_t o[4];
-    if (MODE == 1) {
-      const uint2 mk = *reinterpret_cast<const uint2*>(mask + pos * kCH + c0);
-      const uint16_t mv[4] = {(uint16_t)(mk.x & 0xffff), (uint16_t)(mk.x >> 16), (uint16_t)(mk.y & 0xffff),
-                              (uint16_t)(mk.y >> 16)};
-#pragma unroll
-      for (int j = 0; j < 4; ++j) o[j] = f2bf(bf2f(mv[j]) > 0.0f ? acc[4 * g + j] : 0.0f);
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) o[j] = f2bf(fmaxf(acc[4 * g + j] + bias[c0 + j], 0.0f));
+    for (int q = 0; q < PER; ++q) {
+      const int i = tid + q * NT;
+      const int c = i % G8, x = (i / G8) % kXW, ry = i / (G8 * kXW);
+      const int y = y0 - 1 + ry;
+      const bool ok = i < PLANE && tp >= 0 && tp < T && y >= 0 && y < Y;
+      v[q] = ok ? reinterpret_cast<const uint4*>(in + ((((size_t)n * T + tp) * Y + y) * kXW + x) * CIN)[c]
+                : make_uint4(0u, 0u, 0u, 0u);
     }
-    uint2 pk;
-    pk.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
-    pk.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
-    *reinterpret_cast<uint2*>(out + pos * kCH + c0) = pk;
+  };
+  auto stage = [&](int tp, const uint4 (&v)[PER]) {
+    uint4* sl = xl + (tp & 3) * SLOT;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = tid + q * NT;
+      if (i < PLANE) {
+        const int c = i % G8, x = (i / G8) % kXW, ry = i / (G8 * kXW);
+        const int xs = x + 1;
+        sl[ry * ROW + xs * G8 + (c ^ conv_swz<CIN>(xs))] = v[q];
+      }
+    }
+  };
+  {
+    uint4 v[PER];
+    fetch(t0 - 1, v);
+    stage(t0 - 1 + 4, v);            // slot index uses tp & 3; keep it non-negative
+    fetch(t0, v);
+    stage(t0, v);
+    fetch(t0 + 1, v);
+    stage(t0 + 1, v);
+  }
+  __syncthreads();
+
+  const int x = l & 31, half = l >> 5;
+  int hs[3];
+#pragma unroll
+  for (int dx = 0; dx < 3; ++dx) hs[dx] = half ^ conv_swz<CIN>(x + dx);
+  const int y = y0 + w;
+  const bool row_ok = y < Y;
+  const v8bf* wa = reinterpret_cast<const v8bf*>(wl) + l;
+  for (int t = t0; t < t1; ++t) {
+    uint4 v[PER];
+    fetch(t + 2, v);
+    if (row_ok) {
+      v16f acc = {};
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int tap = s / (CIN / 16), kb = s % (CIN / 16);
+        const int dt = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+        const uint4* rowp = xl + ((t - 1 + dt + 4) & 3) * SLOT + (w + dy) * ROW + (x + dx) * G8;
+        const uint4 bv = rowp[(2 * kb) ^ hs[dx]];
+        v8bf b;
+        __builtin_memcpy(&b, &bv, 16);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[s * kWave], b, acc, 0, 0, 0);
+      }
+      const size_t pos = (((size_t)n * T + t) * Y + y) * kXW + x;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int c0 = 8 * g + 4 * half;
+        uint16_t o[4];
+        if (MODE == 1) {
+          const uint2 mk = *reinterpret_cast<const uint2*>(mask + pos * kCH + c0);
+          const uint16_t mv[4] = {(uint16_t)(mk.x & 0xffff), (uint16_t)(mk.x >> 16), (uint16_t)(mk.y & 0xffff),
+                                  (uint16_t)(mk.y >> 16)};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) o[j] = f2bf(bf2f(mv[j]) > 0.0f ? acc[4 * g + j] : 0.0f);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) o[j] = f2bf(fmaxf(acc[4 * g + j] + bias[c0 + j], 0.0f));
+        }
+        uint2 pk;
+        pk.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
+        pk.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
+        *reinterpret_cast<uint2*>(out + pos * kCH + c0) = pk;
+      }
+    }
+    stage(t + 2, v);                 // slot of plane t - 2, which step t does not read
+    __syncthreads();
   }
 }
 
@@ -381,17 +464,28 @@ __global__ void k_adam(float* __restrict__ th, float* __restrict__ m, float* __r
   th[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// BF16 copies of a conv layer's weights: forward layout [co][tap][ci] and the
-// backward-data layout [ci][26 - tap][co] (transposed channels, flipped taps).
+// BF16 copies of a conv layer's weights in convolution-operand order: element
+// (s, l, j) (K step s, lane l, element j; 16 bytes per lane and step) holds the
+// weight of output channel l % 32 at K index 16 s + 8 (l / 32) + j, K running
+// over (tap, input channel). Forward: W[co][tap][ci]. Backward-data (input
+// gradient as a convolution of the output gradient): output channel = forward
+// input channel, K over (tap', forward output channel) with tap' = 26 - tap
+// (flipped taps, transposed channels).
 __global__ void k_prep_weights(const float* __restrict__ wsrc, int cin, uint16_t* __restrict__ wf,
                                uint16_t* __restrict__ wb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = kCH * kTaps * cin;
   if (i >= total) return;
-  const int co = i / (kTaps * cin), tap = (i / cin) % kTaps, ci = i % cin;
-  const uint16_t b = f2bf(wsrc[i]);
-  wf[i] = b;
-  if (wb) wb[((size_t)ci * kTaps + (kTaps - 1 - tap)) * kCH + co] = b;
+  const int s = i / 512, l = (i / 8) % 64, j = i % 8;
+  const int m = l % 32, kk = 16 * s + 8 * (l / 32) + j;
+  {
+    const int tap = kk / cin, ci = kk % cin;
+    wf[i] = f2bf(wsrc[((size_t)m * kTaps + tap) * cin + ci]);
+  }
+  if (wb) {                                           // cin == 32 here: K = 27 x 32 forward outputs
+    const int tapb = kk / kCH, cof = kk % kCH;
+    wb[i] = f2bf(wsrc[((size_t)cof * kTaps + (kTaps - 1 - tapb)) * cin + m]);
+  }
 }
 
 // ------------------------------------------------------------- cutouts
@@ -427,20 +521,22 @@ __global__ void k_cutouts(const ST* const* __restrict__ cubes, const CutoutDesc*
 }
 
 // --------------------------------------------------------------- launchers
+static unsigned conv_blocks(int N, int T, int Y) {
+  return (unsigned)N * ((Y + kConvYT - 1) / kConvYT) * ((T + kConvTT - 1) / kConvTT);
+}
+
 hipError_t launch_conv_fwd(int cin, const uint16_t* in, const uint16_t* w, const float* bias, uint16_t* out, int N,
                            int T, int Y, hipStream_t st) {
-  const long long rows = (long long)N * T * Y;
-  const unsigned grid = (unsigned)((rows + 3) / 4);
-  if (cin == 16) hipLaunchKernelGGL((k_conv3<16, 0>), dim3(grid), dim3(256), 0, st, in, w, bias, nullptr, out, N, T, Y);
-  else hipLaunchKernelGGL((k_conv3<32, 0>), dim3(grid), dim3(256), 0, st, in, w, bias, nullptr, out, N, T, Y);
+  const dim3 grid(conv_blocks(N, T, Y)), block(kConvWaves * kWave);
+  if (cin == 16) hipLaunchKernelGGL((k_conv3<16, 0>), grid, block, 0, st, in, w, bias, nullptr, out, N, T, Y);
+  else hipLaunchKernelGGL((k_conv3<32, 0>), grid, block, 0, st, in, w, bias, nullptr, out, N, T, Y);
   return hipGetLastError();
 }
 
 hipError_t launch_conv_bwd_data(const uint16_t* dpre, const uint16_t* wb, const uint16_t* mask_act, uint16_t* out, int N,
                                 int T, int Y, hipStream_t st) {
-  const long long rows = (long long)N * T * Y;
-  hipLaunchKernelGGL((k_conv3<32, 1>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, dpre, wb, nullptr, mask_act,
-                     out, N, T, Y);
+  hipLaunchKernelGGL((k_conv3<32, 1>), dim3(conv_blocks(N, T, Y)), dim3(kConvWaves * kWave), 0, st, dpre, wb, nullptr,
+                     mask_act, out, N, T, Y);
   return hipGetLastError();
 }
 
