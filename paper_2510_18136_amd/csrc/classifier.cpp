@@ -162,7 +162,7 @@ extern "C" nsfrb_status nsfrb_classifier_create(const nsfrb_classifier_config* c
     NSFRB_HIP_TRY(dalloc(&c->d_act[l], N * npos * kCh));
   }
   for (auto& p : c->d_dpre) NSFRB_HIP_TRY(dalloc(&p, N * npos * kCh));
-  const size_t items = (size_t)wgrad_items((int)N, cfg->n_time);
+  const size_t items = (size_t)wgrad_items((int)N, cfg->ny);
   NSFRB_HIP_TRY(dalloc(&c->d_part, items * kTap * kCh * kCh));
   NSFRB_HIP_TRY(dalloc(&c->d_part_db, items * kCh));
   NSFRB_HIP_TRY(dalloc(&c->d_h, N * 2 * kCh));

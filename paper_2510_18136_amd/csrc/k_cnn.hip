@@ -176,98 +176,193 @@ __global__ __launch_bounds__(kConvWaves * kWave) void k_conv3(const uint16_t* __
 }
 
 // --------------------------------------------------------- weight gradient
-// Work item = (n, chunk of kTch time planes). Per output row (t, y) the
-// pre-activation gradient row is staged transposed (dT[co][x], so an A operand
-// is one aligned 8-byte read) and the nine input rows of the taps are staged
-// channels-last with a zero halo in x (xr[r][x + 1][ci]); a B operand (four
-// positions of one channel) is four 2-byte reads. Wave w accumulates taps
-// w, w + 4, ... (at most 7) for all (co, ci).
-constexpr int kTch = 8;
-constexpr int kXP = 36;       // transposed row pitch (x = 0..31, multiple of 4)
+// dW[co][tap][ci] = sum over positions of dpre[p][co] * in[p + offset(tap)][ci]
+// and db[co] = sum of dpre[p][co]: per tap a GEMM with M = 32 output channels,
+// N = input channels, K = positions, on v_mfma_f32_32x32x16_bf16.
+//
+// Work item = (sample n, 4 consecutive output rows y0 .. y0+3), streamed over
+// every plane t. K at plane t runs over k = 32 r + x (row y0 + r, input
+// position x). Both operands want eight consecutive k per lane, so the data
+// are staged transposed: input rows y0-1 .. y0+4 of planes t-1, t, t+1 as
+// inT[ci][x] in a 4-slot ring, and the plane's output-gradient rows as three
+// copies dT_dx[co][32 r + x] = dpre[y0 + r][x + 1 - dx][co] (one per x-offset
+// of the taps, zero where x + 1 - dx leaves the row), double-buffered. Wave w
+// takes the three taps (dt, dy) = (w / 3, w % 3), dx = 0..2: per K step one B
+// read and three A reads, all 16 bytes and conflict-free (row pitches padded).
+// The next plane's loads are issued before the matrix work and stored after
+// it. Each item writes its partial sums, which a second kernel adds in a fixed
+// order (deterministic).
+constexpr int kWgR = 4;                    // output rows per item
+constexpr int kWgWaves = 9;                // one per (dt, dy)
+constexpr int kWgRows = kWgR + 2;          // staged input rows per plane
+constexpr int kWgXP = kXW + 8;             // inT row pitch (bf16): 80 bytes
+constexpr int kWgKP = kWgR * kXW + 8;      // dT row pitch (bf16): 272 bytes
+
+int wgrad_items(int N, int Y) { return N * ((Y + kWgR - 1) / kWgR); }
 
 template <int CIN>
-__global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dpre,
-                                                     float* __restrict__ part, float* __restrict__ part_db, int N,
-                                                     int T, int Y) {
-  __shared__ __attribute__((aligned(16))) uint16_t dT[kCH * kXP];
-  __shared__ __attribute__((aligned(16))) uint16_t xr[9 * (kXW + 2) * CIN];
-  const int l = lane_id(), wv = threadIdx.x / 64;
-  const int chunks = (T + kTch - 1) / kTch;
-  const int n = blockIdx.x / chunks, t0 = (blockIdx.x % chunks) * kTch;
-  const int col = l & 31, kq = l >> 5;
-  v16f acc[7];
+__global__ __launch_bounds__(kWgWaves * kWave) void k_conv3_wgrad(const uint16_t* __restrict__ x,
+                                                                  const uint16_t* __restrict__ dpre,
+                                                                  float* __restrict__ part,
+                                                                  float* __restrict__ part_db, int N, int T,
+                                                                  int Y) {
+  constexpr int NT = kWgWaves * kWave;
+  constexpr int G8 = CIN / 8;
+  constexpr int SLOT = kWgRows * CIN * kWgXP;                 // bf16 per ring slot
+  constexpr int DCOPY = kCH * kWgKP;                          // bf16 per dT copy
+  constexpr int IN_CH = kWgRows * kXW * G8;                   // 16-byte chunks per input plane slice
+  constexpr int D_CH = kWgR * kXW * (kCH / 8);                // 16-byte chunks per dpre plane slice
+  constexpr int IN_PER = (IN_CH + NT - 1) / NT;
+  static_assert(D_CH <= NT, "one dpre chunk per thread");
+  __shared__ __attribute__((aligned(16))) uint16_t inT[4 * SLOT];
+  __shared__ __attribute__((aligned(16))) uint16_t dT[2 * 3 * DCOPY];
+  __shared__ float dbs[kCH * (D_CH / (kCH / 8))];              // per-thread bias partials, reduced at the end
+
+  const int n_yb = (Y + kWgR - 1) / kWgR;
+  const int n = blockIdx.x / n_yb, y0 = (blockIdx.x % n_yb) * kWgR;
+  const int tid = threadIdx.x, l = lane_id();
+  const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int dt = w / 3, dy = w % 3;
+
+  // dT entries that no store reaches (the row ends of the shifted copies) stay 0
+  for (int i = tid; i < 2 * 3 * DCOPY; i += NT) dT[i] = 0;
+  __syncthreads();
+
+  auto fetch_in = [&](int tp, uint4 (&v)[IN_PER]) {
 #pragma unroll
-  for (int k = 0; k < 7; ++k) acc[k] = v16f{};
-  float dbsum = 0.f;
-  constexpr int V8 = CIN / 8;              // 16-byte vectors per position
-  for (int t = t0; t < t0 + kTch && t < T; ++t) {
-    for (int y = 0; y < Y; ++y) {
-      __syncthreads();
-      for (int i = threadIdx.x; i < kXW * kCH; i += blockDim.x) {
-        const int xx = i / kCH, c = i % kCH;
-        dT[c * kXP + xx] = dpre[((((size_t)n * T + t) * Y + y) * kXW + xx) * kCH + c];
-      }
-      for (int i = threadIdx.x; i < 9 * (kXW + 2) * V8; i += blockDim.x) {
-        const int r = i / ((kXW + 2) * V8), rem = i % ((kXW + 2) * V8);
-        const int xh = rem / V8, v8 = rem % V8;          // xh = x + 1
-        const int tt = t + r / 3 - 1, yy = y + r % 3 - 1, xs = xh - 1;
-        uint4 v = {0u, 0u, 0u, 0u};
-        if (tt >= 0 && tt < T && yy >= 0 && yy < Y && xs >= 0 && xs < kXW)
-          v = *reinterpret_cast<const uint4*>(x + ((((size_t)n * T + tt) * Y + yy) * kXW + xs) * CIN + v8 * 8);
-        *reinterpret_cast<uint4*>(&xr[(r * (kXW + 2) + xh) * CIN + v8 * 8]) = v;
-      }
-      __syncthreads();
-      if (threadIdx.x < kCH) {
-        float sacc = 0.f;
-        for (int xx = 0; xx < kXW; ++xx) sacc += bf2f(dT[threadIdx.x * kXP + xx]);
-        dbsum += sacc;
-      }
+    for (int q = 0; q < IN_PER; ++q) {
+      const int i = tid + q * NT;
+      const int c = i % G8, xx = (i / G8) % kXW, ry = i / (G8 * kXW);
+      const int y = y0 - 1 + ry;
+      const bool ok = i < IN_CH && tp >= 0 && tp < T && y >= 0 && y < Y;
+      v[q] = ok ? reinterpret_cast<const uint4*>(x + ((((size_t)n * T + tp) * Y + y) * kXW + xx) * CIN)[c]
+                : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto stage_in = [&](int tp, const uint4 (&v)[IN_PER]) {
+    uint16_t* s = inT + ((tp + 4) & 3) * SLOT;
 #pragma unroll
-      for (int k = 0; k < 7; ++k) {
-        const int tap = wv + 4 * k;
-        if (tap < kTaps) {
-          const int r = (tap / 9) * 3 + (tap / 3) % 3, kx = tap % 3;
+    for (int q = 0; q < IN_PER; ++q) {
+      const int i = tid + q * NT;
+      if (i < IN_CH) {
+        const int c = i % G8, xx = (i / G8) % kXW, ry = i / (G8 * kXW);
+        uint16_t* d = s + (ry * CIN + 8 * c) * kWgXP + xx;
+        const uint32_t wv[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
-          for (int s8 = 0; s8 < kXW / 8; ++s8) {
-            const int xb = s8 * 8 + kq * 4;
-            const v4s a = *reinterpret_cast<const v4s*>(&dT[col * kXP + xb]);   // A[co][pos]
-            v4s b = {0, 0, 0, 0};                                                // B[pos][ci]
-            if (col < CIN) {
-              const uint16_t* pb = &xr[(r * (kXW + 2) + xb + kx) * CIN + col];   // input x = xb + kx - 1
-              b[0] = (short)pb[0];
-              b[1] = (short)pb[CIN];
-              b[2] = (short)pb[2 * CIN];
-              b[3] = (short)pb[3 * CIN];
-            }
-            acc[k] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[k], 0, 0, 0);
-          }
+        for (int j = 0; j < 8; ++j) d[j * kWgXP] = (uint16_t)(wv[j / 2] >> (16 * (j & 1)));
+      }
+    }
+  };
+  // dpre plane tp (rows y0 .. y0+3) -> one chunk per thread (8 output channels of one position)
+  const int dc = tid % (kCH / 8), dxp = (tid / (kCH / 8)) % kXW, dr = tid / (kCH / 8 * kXW);
+  auto fetch_d = [&](int tp) {
+    const bool ok = tid < D_CH && tp < T && y0 + dr < Y;
+    return ok ? reinterpret_cast<const uint4*>(dpre + ((((size_t)n * T + tp) * Y + y0 + dr) * kXW + dxp) * kCH)[dc]
+              : make_uint4(0u, 0u, 0u, 0u);
+  };
+  float dbp[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  auto stage_d = [&](int buf, const uint4& v) {
+    if (tid < D_CH) {
+      const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint16_t b = (uint16_t)(wv[j / 2] >> (16 * (j & 1)));
+        dbp[j] += bf2f(b);
+        uint16_t* d = dT + (size_t)buf * 3 * DCOPY + (8 * dc + j) * kWgKP + dr * kXW;
+#pragma unroll
+        for (int ddx = 0; ddx < 3; ++ddx) {
+          const int xs = dxp - 1 + ddx;                      // input position paired with dpre position dxp
+          if (xs >= 0 && xs < kXW) d[ddx * DCOPY + xs] = b;
         }
       }
     }
+  };
+
+  {
+    uint4 v[IN_PER];
+    fetch_in(-1, v);
+    stage_in(-1, v);
+    fetch_in(0, v);
+    stage_in(0, v);
+    fetch_in(1, v);
+    stage_in(1, v);
+    stage_d(0, fetch_d(0));
   }
-  // partial sums of this item, in the parameter layout: part[item][co][tap][ci]
-  float* pb = part + (size_t)blockIdx.x * kTaps * kCH * CIN;
+  __syncthreads();
+
+  v16f acc[3] = {v16f{}, v16f{}, v16f{}};
+  const int col = l & 31, h = l >> 5;
+  for (int t = 0; t < T; ++t) {
+    uint4 vin[IN_PER];
+    fetch_in(t + 2, vin);
+    const uint4 vd = fetch_d(t + 1);
+    const uint16_t* sb = inT + ((t - 1 + dt + 4) & 3) * SLOT + col * kWgXP;      // inT[.][ci = col][x]
+    const uint16_t* sa = dT + (size_t)(t & 1) * 3 * DCOPY + col * kWgKP;         // dT_dx[co = col][k]
 #pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    const int tap = wv + 4 * k;
-    if (tap < kTaps && col < CIN) {
+    for (int r = 0; r < kWgR; ++r) {
+#pragma unroll
+      for (int xh = 0; xh < 2; ++xh) {
+        const int xo = 16 * xh + 8 * h;
+        v8bf b = {};
+        if (col < CIN) __builtin_memcpy(&b, sb + (r + dy) * CIN * kWgXP + xo, 16);
+#pragma unroll
+        for (int ddx = 0; ddx < 3; ++ddx) {
+          v8bf a;
+          __builtin_memcpy(&a, sa + ddx * DCOPY + r * kXW + xo, 16);
+          acc[ddx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[ddx], 0, 0, 0);
+        }
+      }
+    }
+    stage_in(t + 2, vin);            // ring slot of plane t - 2, not read at step t
+    stage_d((t + 1) & 1, vd);        // the other dT buffer
+    __syncthreads();
+  }
+
+  // partial sums of this item, in the parameter layout part[item][co][tap][ci]
+  float* pb = part + (size_t)blockIdx.x * kTaps * kCH * CIN;
+  if (col < CIN) {
+#pragma unroll
+    for (int ddx = 0; ddx < 3; ++ddx) {
+      const int tap = dt * 9 + dy * 3 + ddx;
 #pragma unroll
       for (int rg = 0; rg < 16; ++rg) {
-        const int co = 8 * (rg / 4) + 4 * kq + (rg % 4);
-        pb[((size_t)co * kTaps + tap) * CIN + col] = acc[k][rg];
+        const int co = 8 * (rg / 4) + 4 * h + (rg % 4);
+        pb[((size_t)co * kTaps + tap) * CIN + col] = acc[ddx][rg];
       }
     }
   }
-  if (threadIdx.x < kCH) part_db[(size_t)blockIdx.x * kCH + threadIdx.x] = dbsum;
+  // bias: thread tid holds channels 8 dc .. 8 dc + 7 of its positions
+  if (tid < D_CH) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dbs[(8 * dc + j) * (D_CH / (kCH / 8)) + tid / (kCH / 8)] = dbp[j];
+  }
+  __syncthreads();
+  if (tid < kCH) {
+    float s = 0.f;
+    for (int i = 0; i < D_CH / (kCH / 8); ++i) s += dbs[tid * (D_CH / (kCH / 8)) + i];
+    part_db[(size_t)blockIdx.x * kCH + tid] = s;
+  }
 }
 
-// out[i] = sum over items of part[item][i] (fixed order, deterministic).
-__global__ void k_reduce_items(const float* __restrict__ part, int n_items, int len, float* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= len) return;
+// out[i] = sum over items of part[item][i] in a fixed order (deterministic):
+// a workgroup takes 32 outputs; thread (o, c) adds items c, c + 8, ... of output
+// o, and the eight partial sums are then added in order of c.
+constexpr int kRedOut = 32, kRedPar = 8;
+__global__ __launch_bounds__(kRedOut * kRedPar) void k_reduce_items(const float* __restrict__ part, int n_items,
+                                                                    int len, float* __restrict__ out) {
+  __shared__ float ps[kRedPar][kRedOut];
+  const int o = threadIdx.x % kRedOut, c = threadIdx.x / kRedOut;
+  const int i = blockIdx.x * kRedOut + o;
   float s = 0.f;
-  for (int it = 0; it < n_items; ++it) s += part[(size_t)it * len + i];
-  out[i] = s;
+  if (i < len)
+    for (int it = c; it < n_items; it += kRedPar) s += part[(size_t)it * len + i];
+  ps[c][o] = s;
+  __syncthreads();
+  if (c == 0 && i < len) {
+    float t = ps[0][o];
+    for (int k = 1; k < kRedPar; ++k) t += ps[k][o];
+    out[i] = t;
+  }
 }
 
 // ------------------------------------------------------------------- head
@@ -540,16 +635,16 @@ hipError_t launch_conv_bwd_data(const uint16_t* dpre, const uint16_t* wb, const 
   return hipGetLastError();
 }
 
-int wgrad_items(int N, int T) { return N * ((T + kTch - 1) / kTch); }
-
 hipError_t launch_conv_wgrad(int cin, const uint16_t* x, const uint16_t* dpre, float* part, float* part_db, float* dw,
                              float* db, int N, int T, int Y, hipStream_t st) {
-  const int items = wgrad_items(N, T);
-  if (cin == 16) hipLaunchKernelGGL((k_conv3_wgrad<16>), dim3(items), dim3(256), 0, st, x, dpre, part, part_db, N, T, Y);
-  else hipLaunchKernelGGL((k_conv3_wgrad<32>), dim3(items), dim3(256), 0, st, x, dpre, part, part_db, N, T, Y);
+  const int items = wgrad_items(N, Y);
+  const dim3 block(kWgWaves * kWave);
+  if (cin == 16) hipLaunchKernelGGL((k_conv3_wgrad<16>), dim3(items), block, 0, st, x, dpre, part, part_db, N, T, Y);
+  else hipLaunchKernelGGL((k_conv3_wgrad<32>), dim3(items), block, 0, st, x, dpre, part, part_db, N, T, Y);
   const int len = kTaps * kCH * cin;
-  hipLaunchKernelGGL(k_reduce_items, dim3((len + 255) / 256), dim3(256), 0, st, part, items, len, dw);
-  hipLaunchKernelGGL(k_reduce_items, dim3(1), dim3(kCH), 0, st, part_db, items, kCH, db);
+  hipLaunchKernelGGL(k_reduce_items, dim3((len + kRedOut - 1) / kRedOut), dim3(kRedOut * kRedPar), 0, st, part, items,
+                     len, dw);
+  hipLaunchKernelGGL(k_reduce_items, dim3(1), dim3(kRedOut * kRedPar), 0, st, part_db, items, kCH, db);
   return hipGetLastError();
 }
 

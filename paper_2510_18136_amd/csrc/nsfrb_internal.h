@@ -80,7 +80,7 @@ hipError_t launch_conv_fwd(int cin, const uint16_t* in, const uint16_t* w, const
                            int T, int Y, hipStream_t st);
 hipError_t launch_conv_bwd_data(const uint16_t* dpre, const uint16_t* wb, const uint16_t* mask_act, uint16_t* out, int N,
                                 int T, int Y, hipStream_t st);
-int wgrad_items(int N, int T);
+int wgrad_items(int N, int Y);   // partial-sum items of the weight-gradient kernel
 hipError_t launch_conv_wgrad(int cin, const uint16_t* x, const uint16_t* dpre, float* part, float* part_db, float* dw,
                              float* db, int N, int T, int Y, hipStream_t st);
 int pool_chunks(int npos);   // partial keys per sample written by launch_pool (part holds N * this * 32)
