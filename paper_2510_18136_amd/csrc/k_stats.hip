@@ -32,6 +32,9 @@
 // [0, largest distance], the largest distance being that of the series' minimum
 // or maximum. Ranges that cannot be binned that far (long runs of equal keys)
 // take a general path: the k-th key, then the FP64 values among its ties.
+// Usually the MAD needs no histogram of its own: the median's one-round
+// histogram predicts a narrow bracket of distances around it, and one exact pass
+// checks that the bracket holds the middle ranks (see mad_from_bracket).
 //
 // Normalisation divides in FP64 by Markstein's method: with r = RN(1/sigma)
 // (a correctly rounded division, once per series), q0 = RN(a*r),
@@ -195,17 +198,19 @@ __device__ __forceinline__ Sel select_kth_f32(const Key& key, int k, const Serie
 // every sample of a lower key bin has a smaller value than every sample of the
 // bin holding rank k, and every sample of a higher bin a larger one: once that
 // bin has <= 64 members, their FP64 values sorted across the wave give the
-// answer directly. Returns false (nothing decided) when the range cannot be
-// binned down to such a bin; the caller then takes the general path.
+// answer directly. Returns the number of histogram rounds used, or 0 (nothing
+// decided) when the range cannot be binned down to such a bin; the caller then
+// takes the general path. After a one-round answer, cx.hist still holds the
+// histogram of the whole range [lo, hi].
 template <int V, class Key, class Val>
-__device__ __forceinline__ bool select_values(const Key& key, const Val& val, int k, bool want_second, float lo,
+__device__ __forceinline__ int select_values(const Key& key, const Val& val, int k, bool want_second, float lo,
                                               float hi, const SeriesCtx& cx, double& first, double& second) {
   const int l = lane_id();
   int krem = k;                                    // rank among keys in [lo, hi]
   for (int iter = 0; iter < 48; ++iter) {
-    if (!(lo < hi)) return false;
+    if (!(lo < hi)) return 0;
     const float scale = 256.0f / (hi - lo);
-    if (!(scale > 0.0f && scale < 1e30f)) return false;
+    if (!(scale > 0.0f && scale < 1e30f)) return 0;
     cx.hist[4 * l + 0] = 0; cx.hist[4 * l + 1] = 0; cx.hist[4 * l + 2] = 0; cx.hist[4 * l + 3] = 0;
     wave_lds_sync();
 #pragma unroll
@@ -256,10 +261,10 @@ __device__ __forceinline__ bool select_values(const Key& key, const Val& val, in
       wave_lds_sync();
       c = wave_sort_asc(c);
       first = readlane_d(c, krem);
-      if (!want_second) return true;
+      if (!want_second) return iter + 1;
       if (krem + 1 < (int)cnt) {
         second = readlane_d(c, krem + 1);
-        return true;
+        return iter + 1;
       }
       // rank k is the bin's largest value: rank k + 1 is the smallest value above it
       double nx = __builtin_inf();
@@ -269,7 +274,7 @@ __device__ __forceinline__ bool select_values(const Key& key, const Val& val, in
         if (v > first) nx = fmin(nx, v);
       }
       second = wave_min(nx);
-      return true;
+      return iter + 1;
     }
     float nlo = __builtin_inff(), nhi = -__builtin_inff();
 #pragma unroll
@@ -284,7 +289,88 @@ __device__ __forceinline__ bool select_values(const Key& key, const Val& val, in
     lo = wave_min_f(nlo);
     hi = wave_max_f(nhi);
   }
-  return false;
+  return 0;
+}
+
+// MAD from a bracket (a shortcut; the result is exact or nothing is decided).
+// cx.hist holds the one-round histogram of the samples over [lo, lo + 256/scale]
+// that found the median. Reading it as a piecewise-uniform distribution, two
+// parallel 64-point searches find the distance d at which the count of samples
+// within d of the median reaches the middle rank, and the bracket [d_lo, d_hi]
+// around it is sized to hold about 40 samples. One pass then counts, exactly in
+// FP64, the distances below d_lo and gathers those inside the bracket. If the
+// middle rank(s) fall inside and at most 64 were gathered, their sorted FP64
+// values give the answer; otherwise the caller runs the general selection.
+template <int V>
+__device__ __forceinline__ bool mad_from_bracket(const LdsSeries& x, double med, int k, bool even, float lo,
+                                                 float scale, float dmax, const SeriesCtx& cx, double& mad) {
+  const int l = lane_id();
+  // exclusive prefix counts P[b] in place of the counts (P[256] = total)
+  const uint32_t h0 = cx.hist[4 * l], h1 = cx.hist[4 * l + 1], h2 = cx.hist[4 * l + 2], h3 = cx.hist[4 * l + 3];
+  const uint32_t s4 = h0 + h1 + h2 + h3;
+  const uint32_t incl = wave_incl_scan(s4);
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+  wave_lds_sync();
+  const uint32_t e0 = incl - s4;
+  cx.hist[4 * l] = e0;
+  cx.hist[4 * l + 1] = e0 + h0;
+  cx.hist[4 * l + 2] = e0 + h0 + h1;
+  cx.hist[4 * l + 3] = e0 + h0 + h1 + h2;
+  wave_lds_sync();
+  const float mf = (float)med;
+  auto cdf = [&](float p) {                         // interpolated count of samples below p
+    const float u = (p - lo) * scale;
+    if (!(u > 0.0f)) return 0.0f;
+    if (!(u < 256.0f)) return (float)total;
+    const int b = (int)u;
+    const float pb = (float)cx.hist[b];
+    const float pn = b < 255 ? (float)cx.hist[b + 1] : (float)total;
+    return pb + (u - (float)b) * (pn - pb);
+  };
+  const float target = (float)k + (even ? 1.5f : 1.0f);
+  // coarse: d = dmax (i + 1) / 64; fine: 64 steps inside the first coarse step reaching the target
+  float d = dmax * (float)(l + 1) * (1.0f / 64.0f);
+  uint64_t m = ballot(cdf(mf + d) - cdf(mf - d) >= target);
+  int i = m ? __ffsll((long long)m) - 1 : 63;
+  const float c1 = dmax * (float)(i + 1) * (1.0f / 64.0f), c0 = dmax * (float)i * (1.0f / 64.0f);
+  d = c0 + (c1 - c0) * (float)(l + 1) * (1.0f / 64.0f);
+  m = ballot(cdf(mf + d) - cdf(mf - d) >= target);
+  i = m ? __ffsll((long long)m) - 1 : 63;
+  const float dh = c0 + (c1 - c0) * (float)(i + 1) * (1.0f / 64.0f);
+  // local density (samples per unit distance) on both sides, from the bins there
+  auto dens = [&](float p) {
+    const float u = (p - lo) * scale;
+    if (!(u >= 0.0f && u < 256.0f)) return 0.0f;
+    const int b = (int)u;
+    const float pn = b < 255 ? (float)cx.hist[b + 1] : (float)total;
+    return (pn - (float)cx.hist[b]) * scale;
+  };
+  const float rho = dens(mf + dh) + dens(mf - dh);
+  const float half = rho > 0.0f ? 20.0f / rho : dmax;
+  const double d_lo = fmax(0.0, (double)dh - (double)half), d_hi = (double)dh + (double)half;
+  wave_lds_sync();
+  // exact pass: distances below the bracket, and the ones inside it
+  int below = 0, base = 0;
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const double dv = fabs((double)x(j) - med);     // NaN padding fails both tests
+    below += dv < d_lo;
+    const bool in = dv >= d_lo && dv <= d_hi;
+    const uint64_t mm = ballot(in);
+    const int pos = base + lanes_below(mm);
+    if (in && pos < 64) cx.list[pos] = dv;
+    base += popc64(mm);
+  }
+  below = wave_sum(below);
+  const int need = k + (even ? 1 : 0);               // highest rank needed
+  if (!(below <= k && below + base > need && base <= 64)) return false;
+  wave_lds_sync();
+  double c = (l < base) ? cx.list[l] : __builtin_inf();
+  wave_lds_sync();
+  c = wave_sort_asc(c);
+  const double a = readlane_d(c, k - below);
+  mad = even ? (a + readlane_d(c, k - below + 1)) * 0.5 : a;
+  return true;
 }
 
 // The (rank)-th and (rank+1)-th smallest FP64 values val(j) among the samples
@@ -423,7 +509,8 @@ __device__ __forceinline__ void process_series(const float* xs, int p, int s, in
       const bool even = (n_t & 1) == 0;
       double a = 0.0, b = 0.0;
       auto vx = [&](int j) { return (double)x(j); };
-      if (select_values<V>(x, vx, k1, even, xmin, xmax, cx, a, b))
+      const int rounds = select_values<V>(x, vx, k1, even, xmin, xmax, cx, a, b);
+      if (rounds)
         med = even ? (a + b) * 0.5 : a;
       else
         med = median_via_keys<true, V>(x, vx, cx);
@@ -438,10 +525,12 @@ __device__ __forceinline__ void process_series(const float* xs, int p, int s, in
       // each side of the median)
       const float dhi = fmaxf((float)fabs((double)xmax - med), (float)fabs((double)xmin - med));
       double mad;
-      if (select_values<V>(DistKeys{x, mk}, vd, k1, even, 0.0f, dhi, cx, a, b))
+      if (rounds == 1 && mad_from_bracket<V>(x, mv, k1, even, xmin, 256.0f / (xmax - xmin), dhi, cx, mad)) {
+      } else if (select_values<V>(DistKeys{x, mk}, vd, k1, even, 0.0f, dhi, cx, a, b)) {
         mad = even ? (a + b) * 0.5 : a;
-      else
+      } else {
         mad = median_via_keys<false, V>(DistKeys{x, mk}, vd, cx);
+      }
       sig = kMadToSigma * mad;
       usable = (sig > 0.0) && (sig < __builtin_inf());
     }
