@@ -38,6 +38,15 @@ PEAK_BF16_TFLOPS = 2500.0      # dense BF16 matrix cores (no sparsity)
 PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
+def valid_windows(n_pix, n_t, delays, widths):
+    """Number of (d, w, t, p) windows that lie inside every de-dispersed series."""
+    tot = 0
+    for d in range(delays.shape[0]):
+        L = n_t - int(delays[d].max())
+        tot += sum(max(0, L - int(w) + 1) for w in widths)
+    return tot * n_pix
+
+
 def algorithmic_counts(n_pix, n_sub, n_t, delays, widths, store_bytes):
     """Bytes and FP32 operations of the search stage, from the method's definition.
 
@@ -267,6 +276,83 @@ def bench_classifier(nsfrb, hip, steps=20, warmup=3, batch=64):
                                                  "algorithmic_flop_per_cutout": {"train": train, "infer": fwd}}}
 
 
+def bench_multiscale(nsfrb, hip, synth, x_ptr, meta, n_t, steps, warmup, exact_ms):
+    """The paper's three timescales (native; 5x binned at 5x the DMs; 75x binned
+    without de-dispersion), widths 1-16 samples at each, against the exact
+    search with widths 1..1024, 1200 at the native sampling: cost at survey
+    shape, and the S/N each recovers for pulses of widths 1..1200 samples."""
+    factors, scales, widths = (1, 5, 75), (1.0, 5.0, 0.0), [1, 2, 4, 8, 16]
+    cfg = nsfrb.SearchConfig(meta["nx"], meta["ny"], n_t, meta["freqs"], meta["dms"], widths,
+                             snr_threshold=meta["theta"])
+    ms = nsfrb.MultiScale(cfg, factors, scales)
+    for _ in range(warmup):
+        ms.run(x_ptr, 0)
+    hip.synchronize()
+    tm = hip.Timer()
+    tm.start()
+    for _ in range(steps):
+        ms.run(x_ptr, 0)
+    run_ms = tm.stop() / steps
+    tm.close()
+    ms.close()
+    # S/N recovery on a clean cube: 200 pulses at distinct pixels, no RFI
+    cube, m2 = synth.config2(seed=5, nx=64, ny=64, n_pulses=200, n_spikes=0, n_stripes=0)
+    buf = hip.Buffer(cube.nbytes).upload(cube)
+    ex_cfg = nsfrb.SearchConfig(64, 64, cube.shape[0], m2["freqs"], m2["dms"], m2["widths"], snr_threshold=6.0)
+    ex = nsfrb.Search(ex_cfg)
+    ex.run(buf.ptr, 0)
+    ex_best = ex.best()[0]
+    ex.close()
+    ms2 = nsfrb.MultiScale(nsfrb.SearchConfig(64, 64, cube.shape[0], m2["freqs"], m2["dms"], widths,
+                                              snr_threshold=6.0), factors, scales)
+    ms2.run(buf.ptr, 0)
+    per_scale = np.stack([ms2.scale(i).best()[0] for i in range(len(factors))])
+    ms2.close()
+    buf.close()
+    pix = np.array([j["p"] for j in m2["injections"]])
+    wid = np.array([j["width"] for j in m2["injections"]])
+    inj = np.array([j["snr"] for j in m2["injections"]])
+    e, m = ex_best[pix].astype(np.float64), per_scale[:, pix].max(axis=0).astype(np.float64)
+    bins = {"1-16": (1, 16), "17-80": (17, 80), "81-1200": (81, 1200)}
+    by_width = {}
+    for name, (lo, hi) in bins.items():
+        sel = (wid >= lo) & (wid <= hi)
+        by_width[name] = {"pulses": int(sel.sum()),
+                          "median_snr_ratio_multiscale_over_exact": float(np.median(m[sel] / e[sel])),
+                          "min_snr_ratio": float((m[sel] / e[sel]).min()),
+                          "median_exact_over_injected": float(np.median(e[sel] / inj[sel]))}
+    return {"workload": "survey cube; timescales x1 (32 DMs 0-4000), x5 (32 DMs 0-20000, same shifts), "
+                        "x75 (DM 0); widths 1,2,4,8,16 at each",
+            "ms_per_run": run_ms, "exact_ms_per_step": exact_ms, "speedup_vs_exact": exact_ms / run_ms,
+            "snr_recovery": {"workload": "64x64 px, 16 sub-bands, 2048 samples, 200 pulses (width 1-1200 "
+                                         "log-uniform, S/N 6-50, DM 0-4000), no RFI (seed 5)",
+                             "by_width": by_width,
+                             "detected_exact": int((e >= 6.0).sum()), "detected_multiscale": int((m >= 6.0).sum()),
+                             "median_snr_ratio_multiscale_over_exact": float(np.median(m / e))}}
+
+
+def bench_tiny(nsfrb, hip, synth, reps=200):
+    """Launch-bound tiny workload (32x32 px, 4 sub-bands, 64 samples, 8 DMs, widths 1-16):
+    microseconds per complete run (statistics, search, candidates), back to back."""
+    cube, meta = synth.config1()
+    buf = hip.Buffer(cube.nbytes).upload(cube)
+    cfg = nsfrb.SearchConfig(meta["nx"], meta["ny"], cube.shape[0], meta["freqs"], meta["dms"], meta["widths"],
+                             snr_threshold=meta["theta"])
+    s = nsfrb.Search(cfg)
+    for _ in range(20):
+        s.run(buf.ptr, 0)
+    hip.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(reps):
+        s.run(buf.ptr, 0)
+    hip.synchronize()
+    us = (time.perf_counter() - w0) * 1e6 / reps
+    s.close()
+    buf.close()
+    return {"workload": "32x32 px, 4 sub-bands, 64 samples, 8 DMs 0-1000, widths 1-16 (one pulse)",
+            "us_per_run": us, "runs": reps, "trials_per_s": 32 * 32 * 8 * 5 / (us * 1e-6)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,6 +362,8 @@ def main():
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-classifier", action="store_true")
+    ap.add_argument("--no-paper-grid", action="store_true")
+    ap.add_argument("--no-multiscale", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (counter calibration)")
     ap.add_argument("--traffic-from", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV",
@@ -368,7 +456,8 @@ def main():
                                   "100 pulses, 20 zero-DM spikes, 2 stripes (seed 2)",
                       "pixels": n_pix, "sub_bands": 16, "samples": 2048, "dm_trials": n_dm, "widths": n_w},
            "stage_ms": {"stats_norm": stages[0], "search": stages[1], "candidates": stages[2]},
-           "roofline": roof, "hbm": hbm, "candidates_found": ntot, "search_plan": plan32}
+           "roofline": roof, "hbm": hbm, "candidates_found": ntot, "search_plan": plan32,
+           "trial_samples_per_s": valid_windows(n_pix, cube.shape[0], delays, meta["widths"]) / (ms * 1e-3)}
     s32.close()
     if not args.no_fp16:
         cfg16, s16 = make("f16")
@@ -381,7 +470,38 @@ def main():
                              "search_plan": plan16}
         print(f"[bench] fp16 {ms16:.3f} ms/step, stages {st16.round(3).tolist()} ms, plan {plan16}",
               file=sys.stderr, flush=True)
+    if not args.no_paper_grid:
+        # the same cube on the paper's own grid: 16 DMs 0-4000, widths 1-16 samples
+        pg_dms, pg_w = np.linspace(0.0, 4000.0, 16), [1, 2, 4, 8, 16]
+        pg = {"workload": "survey cube on the paper's grid: 16 DMs 0-4000, widths 1,2,4,8,16",
+              "trials": n_pix * 16 * 5}
+        for store, sb in (("f32", 4), ("f16", 2)):
+            c = nsfrb.SearchConfig(meta["nx"], meta["ny"], cube.shape[0], meta["freqs"], pg_dms, pg_w,
+                                   store_dtype=store, snr_threshold=meta["theta"])
+            sp = nsfrb.Search(c)
+            m, st = timed(sp, args.steps, args.warmup)
+            info = sp.plan_info()
+            sp.close()
+            b2, o2 = algorithmic_counts(n_pix, 16, cube.shape[0], c.delays(), pg_w, sb)
+            ts = st[1] * 1e-3
+            pg[store] = {"ms_per_step": m, "trials_per_s": n_pix * 16 * 5 / (m * 1e-3),
+                         "stage_ms": {"stats_norm": st[0], "search": st[1], "candidates": st[2]},
+                         "search_hbm_GBs": b2 / ts / 1e9, "search_hbm_frac": b2 / ts / 1e9 / PEAK_HBM_GBS,
+                         "search_alu_frac": o2 / ts / 1e12 / PEAK_ALU_TOPS,
+                         "algorithmic_bytes": b2, "algorithmic_ops": o2, "search_plan": info}
+            print(f"[bench] paper grid {store}: {m:.3f} ms/step, search {st[1]:.3f} ms "
+                  f"({pg[store]['search_hbm_frac']:.2f} of HBM peak)", file=sys.stderr, flush=True)
+        out["paper_grid"] = pg
+    if not args.no_multiscale:
+        out["multi_timescale"] = bench_multiscale(nsfrb, hip, synth, x_ptr, meta, cube.shape[0], args.steps,
+                                                  args.warmup, ms)
+        mt = out["multi_timescale"]
+        print(f"[bench] multi-timescale {mt['ms_per_run']:.3f} ms/run ({mt['speedup_vs_exact']:.2f}x the exact "
+              f"search), S/N ratio {mt['snr_recovery']['median_snr_ratio_multiscale_over_exact']:.3f}",
+              file=sys.stderr, flush=True)
     xbuf.close()
+    out["tiny"] = bench_tiny(nsfrb, hip, synth)
+    print(f"[bench] tiny workload {out['tiny']['us_per_run']:.1f} us/run", file=sys.stderr, flush=True)
     if not args.no_batch:
         print("[bench] batched form: generating 64 uneven cubes on the device", file=sys.stderr, flush=True)
         out["batch"] = bench_batch(nsfrb, hip)

@@ -170,6 +170,61 @@ nsfrb_status nsfrb_stage_times_get(nsfrb_search* h, float* ms3);
  * autotuner); host_out holds 5 values. */
 nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* info);
 
+/* ---------------------------------------------------------- multi-timescale
+ * The search at several sampling timescales (section 2.2: besides the native
+ * sampling, the images are binned by 5 and by 75 samples and searched again;
+ * the 5x-binned data are searched at 5x the DM trials, which keeps the shift
+ * table of the native search because a delay in samples scales as DM / dt; the
+ * 75x-binned data bypass de-dispersion, their DM delays fitting in one sample).
+ *
+ * Time binning (runs on the current HIP device): out[t'][s][p] =
+ * RN32(x[t' f][s][p] + x[t' f + 1][s][p] + ... + x[t' f + f - 1][s][p]), the
+ * sum taken in FP64 in that order, for t' < n_time / f (a trailing partial bin
+ * is dropped). d_x is a raw [n_time][n_sub][n_pix] cube of in_dtype; d_out is
+ * FP32 [n_time / f][n_sub][n_pix]. Asynchronous on `stream`. INVALID_ARG for
+ * NULL pointers, dimensions < 1, a dtype outside nsfrb_dtype, or f outside
+ * 1..n_time. */
+nsfrb_status nsfrb_bin_time(const void* d_x, int32_t in_dtype, int32_t n_time, int32_t n_sub, int32_t n_pix,
+                            int32_t factor, float* d_out, void* stream);
+
+typedef struct nsfrb_multiscale nsfrb_multiscale; /* opaque handle */
+
+/* One candidate of a multi-timescale search: the candidate of timescale
+ * `scale` (its DM and width indices refer to that timescale's trial lists;
+ * its TOA is in that timescale's samples). */
+typedef struct {
+  nsfrb_candidate cand;
+  int32_t scale;
+} nsfrb_scale_candidate;
+
+/* Plan n_scales (1..8) searches of one raw TSP cube. Timescale s bins the
+ * cube by factor[s] (>= 1; 1 searches the cube itself) and searches
+ * n_time / factor[s] samples with dt_ms * factor[s], the DM trials of cfg
+ * multiplied by dm_scale[s] (finite, >= 0; 0 means the single trial DM 0,
+ * i.e. no de-dispersion), and cfg's widths, statistics, store dtype,
+ * threshold and K. Binned cubes are FP32 and owned by the handle. Errors as
+ * for nsfrb_search_create (the message names the timescale); UNSUPPORTED
+ * unless cfg->layout is NSFRB_LAYOUT_TSP. */
+nsfrb_status nsfrb_multiscale_create(const nsfrb_search_config* cfg, int32_t n_scales, const int32_t* factor,
+                                     const double* dm_scale, nsfrb_multiscale** out);
+/* Release the handle, its searches and binned cubes. NULL is accepted. */
+nsfrb_status nsfrb_multiscale_destroy(nsfrb_multiscale* h);
+/* Enqueue, for every timescale in order, the binning of d_cube and the search
+ * of the result on `stream`; returns without waiting. d_cube must stay valid
+ * until the stream has passed the run. */
+nsfrb_status nsfrb_multiscale_run(nsfrb_multiscale* h, const void* d_cube, void* stream);
+/* The search handle of timescale `scale` (owned by h, valid until destroy):
+ * every introspection entry point above applies to it (maps, best trial,
+ * noise statistics, normalised cube, stage times). */
+nsfrb_status nsfrb_multiscale_scale(nsfrb_multiscale* h, int32_t scale, nsfrb_search** out);
+/* Wait for the last run and merge the candidate lists of all timescales:
+ * sorted by S/N (descending), then timescale index, then pixel index; the
+ * first K (cfg->max_candidates) are kept and min(K, capacity) written.
+ * *n_total = sum over timescales of the pixels at or above the threshold.
+ * TRUNCATED when capacity is below the kept count; NOT_READY before any run. */
+nsfrb_status nsfrb_multiscale_candidates_get(nsfrb_multiscale* h, nsfrb_scale_candidate* host_out,
+                                             int32_t capacity, int32_t* n_written, int32_t* n_total);
+
 /* ------------------------------------------------------------------ batch
  * Many cubes of uneven shape searched together (the process server of
  * section 2.2 batches search tasks per timescale). All configurations must

@@ -228,3 +228,35 @@ def snr_toa_margin_maps(z_tsp, delays, widths):
                 S2[t, np.arange(npix)] = -np.inf
                 margin[d, iw] = smax[d, iw] - S2.max(axis=0)
     return smax, toa, margin
+
+
+def bin_time(cube_tsp, factor):
+    """Time binning for the longer search timescales (section 2.2: the images
+    are also searched binned by 5 and by 75 samples).
+
+    out[t'][s][p] = x[t' f][s][p] + ... + x[t' f + f - 1][s][p], added in FP64
+    in that order and rounded once to FP32, for t' < n_t // f; a trailing
+    partial bin is dropped (reading: the paper bins whole groups of samples).
+    """
+    x = np.asarray(cube_tsp)
+    f = int(factor)
+    nb = x.shape[0] // f
+    acc = np.zeros((nb,) + x.shape[1:], dtype=np.float64)
+    for k in range(f):
+        acc = acc + x[k:nb * f:f].astype(np.float64)
+    return acc.astype(np.float32)
+
+
+def multiscale_search(cube_tsp, freqs_ghz, f_ref_ghz, dt_ms, dms, widths, nx, factors, dm_scales,
+                      **kw):
+    """The search at several timescales (section 2.2): timescale i bins the raw
+    cube by factors[i] and searches it with dt * factors[i] and the DM trials
+    times dm_scales[i], or DM 0 alone when dm_scales[i] == 0 (the longest
+    timescale bypasses de-dispersion). Returns one `search` result per
+    timescale."""
+    out = []
+    for f, k in zip(factors, dm_scales):
+        xb = np.asarray(cube_tsp) if f == 1 else bin_time(cube_tsp, f)
+        d = np.zeros(1) if k == 0 else np.asarray(dms, dtype=np.float64) * k
+        out.append(search(xb, freqs_ghz, f_ref_ghz, dt_ms * f, d, widths, nx, **kw))
+    return out

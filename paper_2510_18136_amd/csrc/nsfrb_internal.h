@@ -71,6 +71,9 @@ struct BoxcarRec {
   int cube, pixel, t0, width;
   float amp;
 };
+// out[t'][s][p] = RN32(FP64 sum of x[t' factor + k][s][p], k = 0..factor-1 in order), t' < n_t / factor
+hipError_t launch_bin_time(const void* x, int in_dtype, int n_t, int n_sub, int n_pix, int factor, float* out,
+                           hipStream_t st);
 hipError_t launch_inject_many(void* const* cubes, int dtype, int layout, int n_pix, int n_sub, int n_t,
                               const BoxcarRec* recs, const int* offsets, int n, hipStream_t st);
 hipError_t launch_inject_rfi(void* cube, int dtype, int layout, int n_pix, int n_sub, int n_t, int kind, int t0, int len,

@@ -38,6 +38,8 @@ EXPORTS = [
     "nsfrb_classifier_params_get", "nsfrb_classifier_params_set", "nsfrb_classifier_set_lr",
     "nsfrb_classifier_grads_get",
     "nsfrb_classifier_train_step", "nsfrb_classifier_infer", "nsfrb_cutouts_extract",
+    "nsfrb_bin_time", "nsfrb_multiscale_create", "nsfrb_multiscale_destroy", "nsfrb_multiscale_run",
+    "nsfrb_multiscale_scale", "nsfrb_multiscale_candidates_get",
 ]
 
 
@@ -59,6 +61,10 @@ class Config(ctypes.Structure):
 class Candidate(ctypes.Structure):
     _fields_ = [("x", ctypes.c_int32), ("y", ctypes.c_int32), ("dm_index", ctypes.c_int32),
                 ("width_index", ctypes.c_int32), ("toa", ctypes.c_int32), ("snr", ctypes.c_float)]
+
+
+class ScaleCandidate(ctypes.Structure):
+    _fields_ = [("cand", Candidate), ("scale", ctypes.c_int32)]
 
 
 class ClassifierConfig(ctypes.Structure):
@@ -147,6 +153,13 @@ def lib():
             "nsfrb_classifier_infer": ([vp, vp, i32, vp, vp], ctypes.c_int),
             "nsfrb_cutouts_extract": ([vp, ctypes.POINTER(vp), i32, i32, i32, i32, i32, i32, pi32, i32,
                                        ctypes.POINTER(CutoutDesc), i32, vp, vp], ctypes.c_int),
+            "nsfrb_bin_time": ([vp, i32, i32, i32, i32, i32, vp, vp], ctypes.c_int),
+            "nsfrb_multiscale_create": ([ctypes.POINTER(Config), i32, pi32, pd, ctypes.POINTER(vp)], ctypes.c_int),
+            "nsfrb_multiscale_destroy": ([vp], ctypes.c_int),
+            "nsfrb_multiscale_run": ([vp, vp, vp], ctypes.c_int),
+            "nsfrb_multiscale_scale": ([vp, i32, ctypes.POINTER(vp)], ctypes.c_int),
+            "nsfrb_multiscale_candidates_get": ([vp, ctypes.POINTER(ScaleCandidate), i32, pi32, pi32],
+                                                ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -201,6 +214,14 @@ class SearchConfig:
     def n_pix(self):
         return self.nx * self.ny
 
+    def derived(self, n_time, dt_ms, dms, in_dtype):
+        """The same search with another time axis, DM list and input dtype."""
+        c = self.c
+        return SearchConfig(self.nx, self.ny, n_time, self.freqs, dms, self.widths, f_ref_ghz=c.f_ref_ghz,
+                            dt_ms=dt_ms, k_dm_ms=c.k_dm_ms, in_dtype=in_dtype, store_dtype=self.store_dtype,
+                            norm=self.norm, snr_threshold=c.snr_threshold, max_candidates=self.max_candidates,
+                            device=c.device, layout=self.layout)
+
     def validate(self):
         return lib().nsfrb_config_validate(ctypes.byref(self.c))
 
@@ -220,6 +241,72 @@ class SearchConfig:
         return buf.value.decode()
 
 
+def bin_time(d_x, in_dtype, n_time, n_sub, n_pix, factor, d_out, stream=0):
+    """nsfrb_bin_time: FP32 [n_time // factor][n_sub][n_pix] sums of consecutive samples."""
+    check(lib().nsfrb_bin_time(ctypes.c_void_p(int(d_x)), DTYPES[in_dtype], int(n_time), int(n_sub), int(n_pix),
+                               int(factor), ctypes.c_void_p(int(d_out)), ctypes.c_void_p(int(stream))))
+
+
+class MultiScale:
+    """Searches of one raw cube at several timescales (nsfrb_multiscale_*).
+
+    Timescale s bins by factors[s] and searches with dt * factors[s] and the DM
+    trials times dm_scales[s] (0: DM 0 only). The default is the paper's three
+    timescales: native, 5x binned at 5x the DMs, 75x binned without
+    de-dispersion."""
+
+    def __init__(self, cfg: SearchConfig, factors=(1, 5, 75), dm_scales=(1.0, 5.0, 0.0)):
+        self.factors = [int(f) for f in factors]
+        self.dm_scales = [float(d) for d in dm_scales]
+        n = len(self.factors)
+        f_arr = (ctypes.c_int32 * n)(*self.factors)
+        d_arr = (ctypes.c_double * n)(*self.dm_scales)
+        h = ctypes.c_void_p()
+        check(lib().nsfrb_multiscale_create(ctypes.byref(cfg.c), n, f_arr, d_arr, ctypes.byref(h)))
+        self.h, self.cfg = h, cfg
+        self.cfgs = []
+        for f, k in zip(self.factors, self.dm_scales):
+            dms = cfg.dms * k if k != 0.0 else np.zeros(1)
+            self.cfgs.append(cfg.derived(cfg.n_time // f, cfg.c.dt_ms * f, dms, cfg.in_dtype if f == 1 else "f32"))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nsfrb_multiscale_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def run(self, d_cube_ptr, stream=0):
+        check(lib().nsfrb_multiscale_run(self.h, ctypes.c_void_p(int(d_cube_ptr)), ctypes.c_void_p(int(stream))))
+
+    def scale(self, s):
+        """Search view of timescale s (maps, best, noise statistics, z cube...)."""
+        p = ctypes.c_void_p()
+        check(lib().nsfrb_multiscale_scale(self.h, int(s), ctypes.byref(p)))
+        return Search._borrow(self.cfgs[s], p, self)
+
+    def candidates(self, capacity=None):
+        cap = self.cfg.max_candidates if capacity is None else int(capacity)
+        arr = (ScaleCandidate * max(cap, 1))()
+        nw, nt = ctypes.c_int32(), ctypes.c_int32()
+        st = lib().nsfrb_multiscale_candidates_get(self.h, arr, cap, ctypes.byref(nw), ctypes.byref(nt))
+        if st not in (OK, TRUNCATED):
+            check(st)
+        recs = [dict(x=r.cand.x, y=r.cand.y, dm_index=r.cand.dm_index, width_index=r.cand.width_index,
+                     toa=r.cand.toa, snr=r.cand.snr, scale=r.scale) for r in arr[:nw.value]]
+        return recs, nt.value, st
+
+
 class Search:
     """A search plan on one GPU (nsfrb_search_create / run / candidates_get)."""
 
@@ -229,7 +316,17 @@ class Search:
         check(lib().nsfrb_search_create(ctypes.byref(cfg.c), ctypes.byref(h)))
         self.h = h
 
+    @classmethod
+    def _borrow(cls, cfg, handle, owner):
+        """A view of a search handle owned by another object (not destroyed here)."""
+        obj = cls.__new__(cls)
+        obj.cfg, obj.h, obj._owner = cfg, handle, owner
+        return obj
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self.h = None
+            return
         if getattr(self, "h", None):
             lib().nsfrb_search_destroy(self.h)
             self.h = None

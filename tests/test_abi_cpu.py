@@ -133,3 +133,35 @@ def test_pst_layout_rules(L):
     assert bad.validate() == nsfrb.INVALID_ARG
     bad = c2_config(layout="pst")
     assert bad.validate() == nsfrb.INVALID_ARG
+
+
+@pytest.mark.parametrize("factors,dm_scales,kw,status,msg", [
+    ((), (), {}, nsfrb.INVALID_ARG, "n_scales"),
+    ((1, 2, 3, 4, 5, 6, 7, 8, 9), (1,) * 9, {}, nsfrb.INVALID_ARG, "n_scales"),
+    ((1, 0), (1.0, 1.0), {}, nsfrb.INVALID_ARG, "factor 1"),
+    ((1, 4096), (1.0, 1.0), {}, nsfrb.INVALID_ARG, "factor 1"),
+    ((1, 5), (1.0, -5.0), {}, nsfrb.INVALID_ARG, "dm_scale 1"),
+    ((1, 5), (1.0, float("inf")), {}, nsfrb.INVALID_ARG, "dm_scale 1"),
+    ((1, 5), (1.0, 5.0), dict(layout="pst", norm="none", in_dtype="f16", store_dtype="f16"),
+     nsfrb.UNSUPPORTED, "raw"),
+    ((1, 5), (1.0, 5.0), dict(dt_ms=0.0), nsfrb.INVALID_ARG, "dt_ms"),
+])
+def test_multiscale_rejects_bad_plans_before_the_gpu(L, factors, dm_scales, kw, status, msg):
+    with pytest.raises(nsfrb.NsfrbError) as e:
+        nsfrb.MultiScale(c2_config(**kw), factors=factors, dm_scales=dm_scales)
+    assert e.value.status == status
+    assert msg in str(e.value)
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((0, "f32", 100, 4, 16, 5, 1), "NULL"),
+    ((1, "f32", 100, 4, 16, 5, 0), "NULL"),
+    ((1, "f32", 0, 4, 16, 5, 1), "dimensions"),
+    ((1, "f32", 100, 4, 16, 0, 1), "factor"),
+    ((1, "f32", 100, 4, 16, 101, 1), "factor"),
+])
+def test_bin_time_rejects_bad_arguments_before_the_gpu(L, args, msg):
+    with pytest.raises(nsfrb.NsfrbError) as e:
+        nsfrb.bin_time(*args)
+    assert e.value.status == nsfrb.INVALID_ARG
+    assert msg in str(e.value)

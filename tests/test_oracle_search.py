@@ -164,3 +164,56 @@ def test_unquantised_store_keeps_fp64_values():
     assert not np.array_equal(osr.cast_store(z, "f32"), z)
     # the FP32 store differs from the unquantised one by at most half an FP32 ulp per value
     assert np.abs(osr.cast_store(z, "f32") - z).max() <= 2.0 ** -25
+
+
+# ------------------------------------------------------------ time binning
+def test_bin_time_matches_explicit_loops():
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal((23, 3, 4)).astype(np.float32)
+    for f in (1, 2, 5, 7, 23):
+        got = osr.bin_time(x, f)
+        assert got.shape == (23 // f, 3, 4) and got.dtype == np.float32
+        for tb in range(23 // f):
+            for s in range(3):
+                for p in range(4):
+                    acc = 0.0
+                    for k in range(f):
+                        acc += float(x[tb * f + k, s, p])       # Python floats are FP64
+                    assert got[tb, s, p] == np.float32(acc)
+
+
+def test_bin_time_integer_totals_and_identity():
+    rng = np.random.default_rng(22)
+    x = rng.integers(-50, 51, size=(301, 2, 5)).astype(np.float32)
+    b = osr.bin_time(x, 75)                       # 4 whole bins, one sample dropped
+    assert b.shape == (4, 2, 5)
+    np.testing.assert_array_equal(b.astype(np.int64).sum(axis=0), x[:300].astype(np.int64).sum(axis=0))
+    np.testing.assert_array_equal(osr.bin_time(x, 1), x)
+    np.testing.assert_array_equal(osr.bin_time(np.full((10, 1, 1), 0.25, np.float32), 5), np.full((2, 1, 1), 1.25))
+
+
+def test_shift_table_reused_at_five_times_dm():
+    """The paper's footnote: searching 5x-binned data at 5x the DMs keeps the shifts."""
+    freqs = np.linspace(1.311, 1.499, 16)
+    for dms in (np.linspace(0, 4000, 32), np.linspace(171, 4000, 16)):
+        native = delay_table(freqs, freqs.max(), 134.2, dms)
+        binned = delay_table(freqs, freqs.max(), 5 * 134.2, 5 * dms)
+        np.testing.assert_array_equal(native, binned)
+
+
+def test_binned_boxcar_snr_closed_form():
+    """A bin-aligned boxcar of width f*w at DM 0, noiseless with external statistics
+    sqrt(f)*sigma for the binned series, has S/N = A*sqrt(n_sub*f*w) at the coarse
+    timescale: the same as the exact native boxcar of width f*w."""
+    ns, nt, f, w, A, sigma = 4, 600, 75, 4, 0.8, 1.3
+    freqs = np.linspace(1.311, 1.499, ns)
+    x = np.zeros((nt, ns, 1), np.float32)
+    synth.inject_boxcar(x, 0, 150, np.zeros(ns, np.int64), f * w, A * sigma)
+    rs = osr.multiscale_search(x, freqs, freqs.max(), 134.2, [0.0, 500.0], [1, 2, 4, 8], 1,
+                               factors=[1, f], dm_scales=[1.0, 0.0], norm="external",
+                               med=np.zeros((1, ns)), sigma=np.full((1, ns), sigma), theta=0.0)
+    # the coarse search used sigma, not sqrt(f) sigma: rescale its S/N by 1/sqrt(f)
+    coarse = rs[1]["snr_max"][0, 2, 0] / math.sqrt(f)
+    assert coarse == pytest.approx(A * math.sqrt(ns * f * w), rel=1e-6)
+    assert rs[1]["toa"][0, 2, 0] == 150 // f
+    assert rs[1]["delays"].shape == (1, ns) and not rs[1]["delays"].any()
