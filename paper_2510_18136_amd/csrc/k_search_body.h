@@ -258,12 +258,50 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
   const int wq = wv % WPP;                 // this wave's DM chunk: d = wq, wq + WPP, ...
   const int rs = cd.rs, n_sub = cd.n_sub, n_t = cd.n_t;
   const ST neg = from_f32<ST>(kNegInf);
-  // ---- stage the group's rows into LDS, -inf beyond n_t
+  // ---- stage the group's rows into LDS, -inf beyond n_t. A pixel's n_sub x n_t
+  // samples are contiguous in memory: when rows split into whole 16-byte
+  // vectors and the cube is 16-byte aligned, every thread issues all its
+  // vector loads (up to kStageBatch) before storing any, so the staging costs
+  // about one memory latency instead of one per sample.
+  constexpr int VW = 16 / (int)sizeof(ST);          // samples per 16-byte vector
+  constexpr int kStageBatch = 8;
+  const bool vec = (n_t % VW) == 0 && (reinterpret_cast<unsigned long long>(cd.z) & 15ull) == 0;
   for (int k = 0; k < PIX; ++k) {
     const int p = p0 + k;
     ST* dstp = zl + (size_t)k * n_sub * rs;
-    if (p < cd.n_pix) {
-      const ST* zp = cd.z + (size_t)p * n_sub * n_t;
+    if (p >= cd.n_pix) continue;
+    const ST* zp = cd.z + (size_t)p * n_sub * n_t;
+    if (vec) {
+      const int nv = n_sub * n_t / VW;
+      const uint4* src = reinterpret_cast<const uint4*>(zp);
+      for (int v0 = threadIdx.x; v0 < nv; v0 += kStageBatch * blockDim.x) {
+        uint4 buf[kStageBatch];
+#pragma unroll
+        for (int b = 0; b < kStageBatch; ++b) {
+          const int v = v0 + b * (int)blockDim.x;
+          buf[b] = v < nv ? src[v] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int b = 0; b < kStageBatch; ++b) {
+          const int v = v0 + b * (int)blockDim.x;
+          if (v < nv) {
+            const int e = v * VW, s = e / n_t, u = e - s * n_t;
+            // FP32 samples are dwords; 16-bit rows have even pitches and u is a
+            // multiple of VW, so every store below is dword-aligned
+            uint32_t* d = reinterpret_cast<uint32_t*>(dstp + s * rs + u);
+            d[0] = buf[b].x;
+            d[1] = buf[b].y;
+            d[2] = buf[b].z;
+            d[3] = buf[b].w;
+          }
+        }
+      }
+      const int tail = rs - n_t;
+      for (int i = threadIdx.x; i < n_sub * tail; i += blockDim.x) {
+        const int s = i / tail;
+        dstp[s * rs + n_t + (i - s * tail)] = neg;
+      }
+    } else {
       for (int s = 0; s < n_sub; ++s) {
         const ST* src = zp + (size_t)s * n_t;
         ST* dst = dstp + s * rs;

@@ -165,7 +165,7 @@ static int samples_per_lane(int n_time, int store) {
 // Row length in samples: 64 C + the largest searched delay + 1 (whole dwords for FP16).
 static int row_len(int C, int dmax_search, int store) {
   const int rs = 64 * C + dmax_search + 1;
-  return store == NSFRB_F16 ? (rs + 1) & ~1 : rs;
+  return store == NSFRB_F32 ? rs : (rs + 1) & ~1;      // 16-bit rows start on a dword
 }
 static size_t lds_bytes_for(int pix, int n_sub, int rs, int store) {
   return (size_t)pix * n_sub * rs * dtype_size(store);
