@@ -131,8 +131,9 @@ def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, 
         grids[r["Kernel_Name"]] = max(grids[r["Kernel_Name"]], int(r["Grid_Size"]))
     full = max((g for k, g in grids.items() if k.startswith("nsfrb_search_c")), default=0)
     kernels = {}
+    stats_names = ("k_stats_norm<32, float, float>", "_ZN5nsfrb12k_stats_normILi32EffE")   # the survey's variant
     for k in fetch:
-        if k not in write or not (k.startswith("nsfrb_search_c") or "k_stats_norm" in k):
+        if k not in write or not (k.startswith("nsfrb_search_c") or any(n in k for n in stats_names)):
             continue
         if k.startswith("nsfrb_search_c") and grids[k] < full:
             continue
