@@ -112,6 +112,23 @@ nsfrb_status nsfrb_config_validate(const nsfrb_search_config* cfg);
  * rounded half to even, into host_out[n_dm * n_sub]. */
 nsfrb_status nsfrb_plan_delays(const nsfrb_search_config* cfg, int32_t* host_out);
 
+/* Host-only DM-trial grid from a smearing tolerance (section 2.2: the trials
+ * are set by a DM tolerance; the effective width of a pulse is the quadrature
+ * sum of its intrinsic width w_int, the sampling time t_s, the smearing inside
+ * the lowest channel 0.0083 ms * chan_bw_MHz * DM * nu_min^-3 and the residual
+ * band delay 4.15 ms * |DM - trial| * (nu_min^-2 - nu_max^-2)). Rule (the
+ * paper names the tolerance but not the rule): trials start at dm_min; the next
+ * trial is 2h further, h chosen so that a pulse midway between the two has an
+ * effective width exactly tol times its width on a trial; the grid ends with the
+ * first trial >= dm_max. Writes min(count, capacity) trials (ascending) to
+ * host_out and *n_out = count; TRUNCATED when capacity < count; INVALID_ARG for
+ * non-finite values, nu_min <= 0 or >= nu_max, t_s <= 0, w_int or chan_bw < 0,
+ * tol <= 1, dm_min < 0 or > dm_max; UNSUPPORTED when the tolerance cannot be
+ * met (channel smearing outgrowing the residual delay) or past 2^20 trials. */
+nsfrb_status nsfrb_plan_dm_grid(double nu_min_ghz, double nu_max_ghz, double chan_bw_mhz, double t_s_ms,
+                                double w_int_ms, double tol, double dm_min, double dm_max, double* host_out,
+                                int32_t capacity, int32_t* n_out);
+
 /* Create a search plan on cfg->device: validates, plans the delay table,
  * allocates the device workspace (normalised cube, statistics, maps,
  * candidates) and uploads the tables. On failure *out is NULL. */

@@ -152,6 +152,47 @@ std::string single_kernel_name(const KernelClass& k);
 // apart hit distinct LDS banks. FP16 rows are read two samples per dword and C
 // is even with C/2 odd: every lane then starts on the same half of a dword (the
 // parity of the delay) and lanes C/2 dwords apart hit distinct banks.
+// DM-trial grid from a smearing tolerance (see nsfrb.h): with A = 4.15 ms *
+// (nu_min^-2 - nu_max^-2), B = 0.0083 ms * dnu * nu_min^-3, C^2 = W_int^2 + t_s^2
+// and q = tol^2 - 1, the half spacing h after trial D solves
+// A^2 h^2 = q (C^2 + B^2 (D + h)^2), a quadratic with one positive root.
+extern "C" nsfrb_status nsfrb_plan_dm_grid(double nu_min_ghz, double nu_max_ghz, double chan_bw_mhz, double t_s_ms,
+                                           double w_int_ms, double tol, double dm_min, double dm_max,
+                                           double* host_out, int32_t capacity, int32_t* n_out) {
+  g_last_error.clear();
+  const double v[] = {nu_min_ghz, nu_max_ghz, chan_bw_mhz, t_s_ms, w_int_ms, tol, dm_min, dm_max};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(NSFRB_ERR_INVALID_ARG, "every parameter must be finite");
+  if (!(nu_min_ghz > 0.0 && nu_max_ghz > nu_min_ghz))
+    return fail(NSFRB_ERR_INVALID_ARG, "need 0 < nu_min < nu_max");
+  if (!(chan_bw_mhz >= 0.0 && t_s_ms > 0.0 && w_int_ms >= 0.0 && tol > 1.0))
+    return fail(NSFRB_ERR_INVALID_ARG, "need chan_bw >= 0, t_s > 0, w_int >= 0 and tol > 1");
+  if (!(dm_min >= 0.0 && dm_max >= dm_min)) return fail(NSFRB_ERR_INVALID_ARG, "need 0 <= dm_min <= dm_max");
+  if (capacity < 0 || (capacity > 0 && !host_out) || !n_out) return fail(NSFRB_ERR_INVALID_ARG, "bad output buffer");
+  const double A = 4.15 * (1.0 / (nu_min_ghz * nu_min_ghz) - 1.0 / (nu_max_ghz * nu_max_ghz));
+  const double B = 0.0083 * chan_bw_mhz / (nu_min_ghz * nu_min_ghz * nu_min_ghz);
+  const double C2 = w_int_ms * w_int_ms + t_s_ms * t_s_ms;
+  const double q = tol * tol - 1.0;
+  const double a2 = A * A - q * B * B;
+  if (!(a2 > 0.0))
+    return fail(NSFRB_ERR_UNSUPPORTED, "tolerance unattainable: channel smearing grows as fast as the residual delay");
+  constexpr int kMaxTrials = 1 << 20;
+  int n = 0;
+  double d = dm_min;
+  for (;;) {
+    if (n < capacity) host_out[n] = d;
+    ++n;
+    if (d >= dm_max) break;
+    if (n >= kMaxTrials) return fail(NSFRB_ERR_UNSUPPORTED, "more than 2^20 trials");
+    const double bd = q * B * B * d;
+    const double h = (bd + std::sqrt(bd * bd + a2 * q * (C2 + B * B * d * d))) / a2;
+    d += 2.0 * h;
+  }
+  *n_out = n;
+  if (n > capacity) return fail(NSFRB_ERR_TRUNCATED, "capacity below the number of trials");
+  return NSFRB_OK;
+}
+
 static int samples_per_lane(int n_time, int store) {
   int c = (n_time + 64) / 64;
   if (store == NSFRB_F16) {

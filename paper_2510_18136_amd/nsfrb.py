@@ -39,7 +39,7 @@ EXPORTS = [
     "nsfrb_classifier_grads_get",
     "nsfrb_classifier_train_step", "nsfrb_classifier_infer", "nsfrb_cutouts_extract",
     "nsfrb_bin_time", "nsfrb_multiscale_create", "nsfrb_multiscale_destroy", "nsfrb_multiscale_run",
-    "nsfrb_multiscale_scale", "nsfrb_multiscale_candidates_get",
+    "nsfrb_multiscale_scale", "nsfrb_multiscale_candidates_get", "nsfrb_plan_dm_grid",
 ]
 
 
@@ -154,6 +154,7 @@ def lib():
             "nsfrb_cutouts_extract": ([vp, ctypes.POINTER(vp), i32, i32, i32, i32, i32, i32, pi32, i32,
                                        ctypes.POINTER(CutoutDesc), i32, vp, vp], ctypes.c_int),
             "nsfrb_bin_time": ([vp, i32, i32, i32, i32, i32, vp, vp], ctypes.c_int),
+            "nsfrb_plan_dm_grid": ([ctypes.c_double] * 8 + [pd, i32, pi32], ctypes.c_int),
             "nsfrb_multiscale_create": ([ctypes.POINTER(Config), i32, pi32, pd, ctypes.POINTER(vp)], ctypes.c_int),
             "nsfrb_multiscale_destroy": ([vp], ctypes.c_int),
             "nsfrb_multiscale_run": ([vp, vp, vp], ctypes.c_int),
@@ -239,6 +240,18 @@ class SearchConfig:
         if r < 0:
             raise NsfrbError(DEVICE, last_error())
         return buf.value.decode()
+
+
+def plan_dm_grid(nu_min_ghz, nu_max_ghz, chan_bw_mhz, t_s_ms, w_int_ms, tol, dm_min, dm_max):
+    """nsfrb_plan_dm_grid: DM trials from a smearing tolerance (host only)."""
+    n = ctypes.c_int32()
+    args = [float(v) for v in (nu_min_ghz, nu_max_ghz, chan_bw_mhz, t_s_ms, w_int_ms, tol, dm_min, dm_max)]
+    st = lib().nsfrb_plan_dm_grid(*args, None, 0, ctypes.byref(n))
+    if st not in (OK, TRUNCATED):
+        check(st)
+    out = np.zeros(n.value, np.float64)
+    check(lib().nsfrb_plan_dm_grid(*args, _ptr(out, ctypes.c_double), n.value, ctypes.byref(n)))
+    return out
 
 
 def bin_time(d_x, in_dtype, n_time, n_sub, n_pix, factor, d_out, stream=0):

@@ -165,3 +165,43 @@ def test_bin_time_rejects_bad_arguments_before_the_gpu(L, args, msg):
         nsfrb.bin_time(*args)
     assert e.value.status == nsfrb.INVALID_ARG
     assert msg in str(e.value)
+
+
+@pytest.mark.parametrize("args", [
+    (1.311, 1.499, 11.71875, 134.2, 0.0, 1.6, 0.0, 4000.0),
+    (1.311, 1.499, 11.71875, 671.0, 0.0, 1.6, 0.0, 20000.0),
+    (1.311, 1.499, 0.0, 134.2, 6.6, 1.25, 171.0, 4000.0),
+    (0.4, 0.8, 0.39, 0.98, 1.0, 1.1, 0.0, 3000.0),
+    (1.311, 1.499, 11.71875, 134.2, 0.0, 1.6, 500.0, 500.0),
+])
+def test_dm_grid_matches_oracle(L, args):
+    from oracle import dmgrid
+    got = nsfrb.plan_dm_grid(*args)
+    nu_min, nu_max, dnu, t_s, w_int, tol, lo, hi = args
+    ref = dmgrid.dm_grid((nu_min, nu_max), dnu, t_s, w_int, tol, lo, hi)
+    assert len(got) == len(ref)
+    np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("args,status", [
+    ((1.311, 1.311, 11.7, 134.2, 0.0, 1.6, 0.0, 4000.0), nsfrb.INVALID_ARG),
+    ((1.311, 1.499, 11.7, 0.0, 0.0, 1.6, 0.0, 4000.0), nsfrb.INVALID_ARG),
+    ((1.311, 1.499, 11.7, 134.2, 0.0, 1.0, 0.0, 4000.0), nsfrb.INVALID_ARG),
+    ((1.311, 1.499, 11.7, 134.2, 0.0, 1.6, 10.0, 5.0), nsfrb.INVALID_ARG),
+    ((1.311, 1.499, float("nan"), 134.2, 0.0, 1.6, 0.0, 4000.0), nsfrb.INVALID_ARG),
+    ((1.311, 1.3111, 500.0, 134.2, 0.0, 3.0, 0.0, 4000.0), nsfrb.UNSUPPORTED),
+])
+def test_dm_grid_rejects(L, args, status):
+    with pytest.raises(nsfrb.NsfrbError) as e:
+        nsfrb.plan_dm_grid(*args)
+    assert e.value.status == status
+
+
+def test_dm_grid_truncation_reports_the_count(L):
+    import ctypes
+    n = ctypes.c_int32()
+    out = (ctypes.c_double * 2)()
+    st = L.nsfrb_plan_dm_grid(1.311, 1.499, 11.71875, 134.2, 0.0, 1.6, 0.0, 4000.0, out, 2, ctypes.byref(n))
+    assert st == nsfrb.TRUNCATED and n.value == len(nsfrb.plan_dm_grid(1.311, 1.499, 11.71875, 134.2, 0.0, 1.6,
+                                                                         0.0, 4000.0)) > 2
+    assert out[0] == 0.0 and out[1] > 0.0
