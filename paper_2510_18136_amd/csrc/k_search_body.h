@@ -240,7 +240,7 @@ struct CubeDesc {
 // held in `cur` and calls rep(width_index, window_sums) for its widths; the
 // passes together report every width once (NSFRB_NPASS passes).
 template <int C, class R>
-__device__ void nsfrb_chain(int pass, float (&cur)[C], R& rep);
+__device__ __forceinline__ void nsfrb_chain(int pass, float (&cur)[C], R& rep);
 
 namespace nsfrb {
 

@@ -55,6 +55,17 @@ static constexpr int kMaxDm = 256;
 static constexpr int kMaxWidth = 32;
 static constexpr int kMaxCand = 4096;
 static constexpr int kMaxAccumulators = 3;     // non-power-of-two widths open at once
+static constexpr int kMaxScratchPerLane = 64;  // bytes of register spill a launched search kernel may use
+
+// Largest per-lane scratch (register spill) a search kernel may have to be
+// launched: a few dozen bytes of spill run correctly and fast; kernels whose
+// private segment approaches the runtime's per-thread stack limit are never
+// launched (such a kernel, 1.9 KB per lane, was rejected at dispatch).
+static int scratch_allowance() {
+  size_t stack = 0;
+  if (hipDeviceGetLimit(&stack, hipLimitStackSize) != hipSuccess) return 0;
+  return (int)std::min<size_t>(stack, (size_t)kMaxScratchPerLane);
+}
 static constexpr size_t kLdsBudget = 160 * 1024 - 1024;
 
 static size_t dtype_size(int dt) { return dt == DT_F32 ? 4 : 2; }
@@ -215,10 +226,11 @@ static size_t lds_bytes_for(int pix, int n_sub, int rs, int store) {
 // Emit the boxcar plan: power-of-two levels by pairwise doubling, other
 // widths as sums of the level windows of their binary digits. A width that
 // is not a power of two needs an accumulator from its lowest to its highest
-// binary digit; widths are split into passes so that at most
-// kMaxAccumulators accumulators are open at any level of a pass (each extra
-// pass re-forms the de-dispersed series). Power-of-two widths go in pass 0.
-static nsfrb_status gen_chain(const std::vector<int>& widths, std::string& out, int* npass_out = nullptr) {
+// binary digit; widths are split into passes so that at most max_acc
+// (<= kMaxAccumulators) accumulators are open at any level of a pass (each
+// extra pass re-forms the de-dispersed series). Power-of-two widths go in pass 0.
+static nsfrb_status gen_chain(const std::vector<int>& widths, std::string& out, int* npass_out = nullptr,
+                              int max_acc = kMaxAccumulators) {
   const int nw = (int)widths.size();
   struct Acc { int iw, w, lo, hi, pass, slot, off; };
   std::vector<Acc> accs;
@@ -235,7 +247,7 @@ static nsfrb_status gen_chain(const std::vector<int>& widths, std::string& out, 
     for (int p = 0; p < (int)passes.size() && a.pass < 0; ++p) {
       for (int s = 0; s < (int)passes[p].size(); ++s)
         if (passes[p][s] < a.lo) { a.pass = p; a.slot = s; passes[p][s] = a.hi; break; }
-      if (a.pass < 0 && (int)passes[p].size() < kMaxAccumulators) {
+      if (a.pass < 0 && (int)passes[p].size() < max_acc) {
         a.pass = p; a.slot = (int)passes[p].size(); passes[p].push_back(a.hi);
       }
     }
@@ -243,9 +255,9 @@ static nsfrb_status gen_chain(const std::vector<int>& widths, std::string& out, 
   }
   const int npass = (int)passes.size();
   std::ostringstream o;
-  o << "template <int C, class R>\n__device__ void nsfrb_chain(int pass, float (&a0)[C], R& rep) {\n";
+  o << "template <int C, class R>\n__device__ __forceinline__ void nsfrb_chain(int pass, float (&a0)[C], R& rep) {\n";
   o << "  using namespace nsfrb;\n  float a1[C];\n";
-  for (int s = 0; s < kMaxAccumulators; ++s) o << "  float acc" << s << "[C];\n";
+  for (int s = 0; s < max_acc; ++s) o << "  float acc" << s << "[C];\n";
   o << "  switch (pass) {\n";
   for (int p = 0; p < npass; ++p) {
     int maxb = 0;
@@ -429,7 +441,11 @@ extern "C" int nsfrb_debug_plan_source(const nsfrb_search_config* cfg, char* out
   }
   std::string chain;
   int npass = 1;
-  if (gen_chain(std::vector<int>(cfg->width, cfg->width + cfg->n_width), chain, &npass) != NSFRB_OK) return -1;
+  // NSFRB_DEBUG_MAX_ACC=n emits the plan with at most n accumulators per pass (inspection of register use)
+  int max_acc = kMaxAccumulators;
+  if (const char* e = std::getenv("NSFRB_DEBUG_MAX_ACC")) max_acc = std::max(1, std::min(kMaxAccumulators, std::atoi(e)));
+  if (gen_chain(std::vector<int>(cfg->width, cfg->width + cfg->n_width), chain, &npass, max_acc) != NSFRB_OK)
+    return -1;
   const std::string src = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, ks);
   if (out && cap > 0) std::snprintf(out, (size_t)cap, "%s", src.c_str());
   if (compile) {
@@ -446,6 +462,7 @@ struct nsfrb_search {
   std::vector<int32_t> widths, delays, dmaxv;
   int n_pix = 0, device = 0;
   int C = 0, rs = 0, pix = 1, nw = 8;  // chosen kernel class and LDS row length
+  int max_acc = kMaxAccumulators;      // accumulators per pass of the boxcar plan (no register spills)
   size_t lds_bytes = 0;
   std::string source;                  // generated search translation unit
   hipModule_t mod = nullptr;
@@ -521,17 +538,40 @@ extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfr
   std::vector<KernelClass> ks = plan_candidates(h->C, cfg->n_dm, cfg->n_sub, h->rs, cfg->store_dtype);
   if (ks.empty())
     return fail(NSFRB_ERR_UNSUPPORTED, "n_sub x (padded n_time + max delay) does not fit in LDS for this store dtype");
-  std::string chain;
-  int npass = 1;
-  st = gen_chain(h->widths, chain, &npass);
-  if (st != NSFRB_OK) return st;
-  h->source = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, {});
   const char* force = std::getenv("NSFRB_FORCE_ALLOC_FAIL");
   if (force && std::atoi(force) != 0) return fail(NSFRB_ERR_OUT_OF_MEMORY, "allocation failure forced by NSFRB_FORCE_ALLOC_FAIL");
 
   HIP_TRY(hipSetDevice(h->device));
-  st = load_module(h->device, h->source, &h->mod);
-  if (st != NSFRB_OK) return st;
+  // Only kernels that keep the boxcar chain in registers (up to a few dozen
+  // bytes of spill) are ever launched: each compiled candidate's scratch use is
+  // queried and a heavily spilling one is dropped. If every shape spills, the
+  // plan is regenerated with fewer accumulators per pass (more passes, each
+  // re-forming the de-dispersed series) before the configuration is refused.
+  const int allowance = scratch_allowance();
+  std::vector<KernelClass> usable;
+  for (int max_acc = kMaxAccumulators; max_acc >= 1 && usable.empty(); --max_acc) {
+    std::string chain;
+    int npass = 1;
+    st = gen_chain(h->widths, chain, &npass, max_acc);
+    if (st != NSFRB_OK) return st;
+    h->source = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, {});
+    st = load_module(h->device, h->source, &h->mod);
+    if (st != NSFRB_OK) return st;
+    for (const KernelClass& k : ks) {
+      hipFunction_t fn = nullptr;
+      HIP_TRY(hipModuleGetFunction(&fn, h->mod, single_kernel_name(k).c_str()));
+      int scratch = 0;
+      HIP_TRY(hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn));
+      if (scratch <= allowance) usable.push_back(k);
+    }
+    h->max_acc = max_acc;
+  }
+  if (usable.empty())
+    return fail(NSFRB_ERR_UNSUPPORTED, "every kernel shape for " + std::to_string(h->C) +
+                                           " samples per lane and these widths would spill more than " +
+                                           std::to_string(allowance) +
+                                           " bytes of registers per lane (n_time too long for the width list)");
+  ks = usable;
   const size_t n_pix = (size_t)h->n_pix, ns = (size_t)cfg->n_sub, nt = (size_t)cfg->n_time;
   const size_t nmaps = (size_t)cfg->n_dm * cfg->n_width * n_pix;
   HIP_TRY(dalloc(&h->d_delays, h->delays.size()));
@@ -982,7 +1022,9 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
   }
   std::string chain;
   int npass = 1;
-  nsfrb_status st = gen_chain(b->cubes[0]->widths, chain, &npass);
+  int max_acc = kMaxAccumulators;
+  for (const nsfrb_search* h : b->cubes) max_acc = std::min(max_acc, h->max_acc);
+  nsfrb_status st = gen_chain(b->cubes[0]->widths, chain, &npass, max_acc);
   if (st != NSFRB_OK) return st;
   HIP_TRY(hipSetDevice(b->device));
   std::vector<KernelClass> ks;
@@ -994,6 +1036,11 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
   for (size_t c = 0; c < b->classes.size(); ++c) {
     BatchClass& bc = b->classes[c];
     HIP_TRY(hipModuleGetFunction(&bc.fn, b->mod, ("nsfrb_batch_kernel_" + std::to_string(c)).c_str()));
+    int scratch = 0;
+    HIP_TRY(hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, bc.fn));
+    if (scratch > scratch_allowance())
+      return fail(NSFRB_ERR_UNSUPPORTED, "the persistent kernel of class " + std::to_string(c) +
+                                             " would spill more registers than a search kernel may");
     // a persistent grid of as many workgroups as this class's kernel keeps resident
     int per_cu = 0;
     HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bc.fn, 64 * bc.k.NW, bc.lds));

@@ -227,24 +227,40 @@ def test_noise_stats_exact(kind, nt):
     compare(g, o, cfg)
 
 
-# The library's maxima: 4096 samples, 256 DM trials, 32 widths (up to the whole
-# series), K = 4096, with the most sub-bands whose per-pixel LDS tile still fits
-# (9 in FP32, 18 in 16-bit stores); a few pixels keep the oracle to seconds.
+# The library's maxima: 4096 samples, 256 DM trials, K = 4096, with the most
+# sub-bands whose per-pixel LDS tile still fits (9 in FP32, 18 in 16-bit
+# stores), and the longest width lists whose boxcar chain stays in registers:
+# 13 widths up to 4096 samples, or 29 widths (many of them not powers of two)
+# at 2048 samples. A few pixels keep the oracle to seconds.
+W_MAX = [1, 2, 3, 4, 5, 6, 7, 8, 9, 11, 13, 16, 20, 23, 30, 32, 40, 47, 64, 95, 128, 191, 256, 383, 512, 767,
+         1024, 1535, 2048, 3000, 4000, 4096]
+
+
 @pytest.mark.parametrize("store,ns", [("f32", 9), ("f16", 18), ("bf16", 18)])
-def test_maximum_sizes(store, ns):
-    rng = np.random.default_rng(4096 + ns)
-    nt, nx, ny = 4096, 3, 2
-    widths = [1, 2, 3, 4, 5, 6, 7, 8, 9, 11, 13, 16, 20, 23, 30, 32, 40, 47, 64, 95, 128, 191, 256, 383, 512,
-              767, 1024, 1535, 2048, 3000, 4000, 4096]
+@pytest.mark.parametrize("nt,widths", [(4096, [1 << k for k in range(13)] + [3000]),
+                                       (2048, [w for w in W_MAX if w <= 2048])])
+def test_maximum_sizes(store, ns, nt, widths):
+    rng = np.random.default_rng(nt + ns + len(widths))
+    nx, ny = 3, 2
     cube = rng.standard_normal((nt, ns, nx * ny)).astype(np.float32)
     freqs = np.linspace(1.311, 1.499, ns)
     off = synth.arrival_offsets(800.0, freqs, freqs.max(), synth.DT_MS)
-    synth.inject_boxcar(cube, 4, 1000, off, 700, 0.3)
+    synth.inject_boxcar(cube, 4, nt // 4, off, 700, 0.3)
     cfg = nsfrb.SearchConfig(nx, ny, nt, freqs, np.linspace(0, 2000, 256), widths, store_dtype=store,
                              snr_threshold=3.0, max_candidates=4096)
     g, o = run_gpu(cube, cfg), oracle_run(cube, cfg)
     compare(g, o, cfg, tol=TOL if store == "f32" else 2e-4)
     assert len(g["cands"]) == g["n_total"] <= nx * ny
+
+
+def test_plan_that_would_spill_is_refused():
+    """4096 samples with 32 widths: every kernel shape would spill hundreds of bytes of
+    registers per lane; the plan is refused when it is created (no kernel is launched)."""
+    cfg = nsfrb.SearchConfig(3, 2, 4096, np.linspace(1.311, 1.499, 9), np.linspace(0, 2000, 256), W_MAX,
+                             snr_threshold=3.0, max_candidates=4096)
+    with pytest.raises(nsfrb.NsfrbError) as e:
+        nsfrb.Search(cfg)
+    assert e.value.status == nsfrb.UNSUPPORTED and "spill" in str(e.value)
 
 
 def test_no_valid_window_and_invalid_trials():
