@@ -130,8 +130,13 @@ nsfrb_status nsfrb_plan_dm_grid(double nu_min_ghz, double nu_max_ghz, double cha
                                 int32_t capacity, int32_t* n_out);
 
 /* Create a search plan on cfg->device: validates, plans the delay table,
- * allocates the device workspace (normalised cube, statistics, maps,
- * candidates) and uploads the tables. On failure *out is NULL. */
+ * compiles the search kernel for this plan, allocates the device workspace
+ * (normalised cube, statistics, maps, candidates) and uploads the tables. On
+ * failure *out is NULL. UNSUPPORTED also when a pixel's rows do not fit in LDS,
+ * or when every kernel shape would keep too little of the boxcar chain in
+ * registers (more than 64 bytes of spill per lane: n_time too long for the
+ * width list, e.g. 4096 samples with 32 widths); such a kernel is never
+ * launched. */
 nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfrb_search** out);
 
 /* Release everything the handle owns. NULL is accepted. */
