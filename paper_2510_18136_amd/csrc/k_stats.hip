@@ -90,6 +90,25 @@ struct DistKeys {
   __device__ __forceinline__ float operator()(int j) const { return (float)fabs((double)x(j) - med); }
 };
 
+// Passes that write LDS (histogram atomics, candidate lists) read their keys
+// kChunk registers at a time ahead of that work: the compiler does not move a
+// read of the series above an LDS write that might alias it, so without the
+// grouping every sample would wait a full LDS round trip.
+constexpr int kChunk = 8;
+template <int V, class Key, class Fn>
+__device__ __forceinline__ void for_each_key(const Key& key, Fn&& fn) {
+#pragma unroll
+  for (int j0 = 0; j0 < V; j0 += kChunk) {
+    float v[kChunk];
+#pragma unroll
+    for (int b = 0; b < kChunk; ++b)
+      if (j0 + b < V) v[b] = key(j0 + b);
+#pragma unroll
+    for (int b = 0; b < kChunk; ++b)
+      if (j0 + b < V) fn(j0 + b, v[b]);
+  }
+}
+
 // k-th smallest (0-based) of the FP32 keys key(j). Registers past the end of
 // the series hold NaN, which fails every comparison and is ignored by
 // fminf/fmaxf, so they never take part.
@@ -213,15 +232,13 @@ __device__ __forceinline__ int select_values(const Key& key, const Val& val, int
     if (!(scale > 0.0f && scale < 1e30f)) return 0;
     cx.hist[4 * l + 0] = 0; cx.hist[4 * l + 1] = 0; cx.hist[4 * l + 2] = 0; cx.hist[4 * l + 3] = 0;
     wave_lds_sync();
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-      const float v = key(j);
+    for_each_key<V>(key, [&](int, float v) {
       if (v >= lo && v <= hi) {
         int b = (int)((v - lo) * scale);
         b = b > 255 ? 255 : b;
         atomicAdd(&cx.hist[b], 1u);
       }
-    }
+    });
     wave_lds_sync();
     const uint32_t h0 = cx.hist[4 * l], h1 = cx.hist[4 * l + 1], h2 = cx.hist[4 * l + 2], h3 = cx.hist[4 * l + 3];
     const uint32_t s4 = h0 + h1 + h2 + h3;
@@ -243,9 +260,7 @@ __device__ __forceinline__ int select_values(const Key& key, const Val& val, int
     krem = (int)(r - before);
     if (cnt <= 64) {
       int base = 0;
-#pragma unroll
-      for (int j = 0; j < V; ++j) {
-        const float v = key(j);
+      for_each_key<V>(key, [&](int j, float v) {
         bool mem = false;
         if (v >= lo && v <= hi) {
           int b = (int)((v - lo) * scale);
@@ -255,7 +270,7 @@ __device__ __forceinline__ int select_values(const Key& key, const Val& val, int
         const uint64_t mm = ballot(mem);
         if (mem) cx.list[base + lanes_below(mm)] = val(j);
         base += popc64(mm);
-      }
+      });
       wave_lds_sync();
       double c = (l < (int)cnt) ? cx.list[l] : __builtin_inf();
       wave_lds_sync();
@@ -351,16 +366,15 @@ __device__ __forceinline__ bool mad_from_bracket(const LdsSeries& x, double med,
   wave_lds_sync();
   // exact pass: distances below the bracket, and the ones inside it
   int below = 0, base = 0;
-#pragma unroll
-  for (int j = 0; j < V; ++j) {
-    const double dv = fabs((double)x(j) - med);     // NaN padding fails both tests
+  for_each_key<V>(x, [&](int, float xv) {
+    const double dv = fabs((double)xv - med);       // NaN padding fails both tests
     below += dv < d_lo;
     const bool in = dv >= d_lo && dv <= d_hi;
     const uint64_t mm = ballot(in);
     const int pos = base + lanes_below(mm);
     if (in && pos < 64) cx.list[pos] = dv;
     base += popc64(mm);
-  }
+  });
   below = wave_sum(below);
   const int need = k + (even ? 1 : 0);               // highest rank needed
   if (!(below <= k && below + base > need && base <= 64)) return false;
