@@ -247,6 +247,21 @@ nsfrb_status nsfrb_multiscale_scale(nsfrb_multiscale* h, int32_t scale, nsfrb_se
 nsfrb_status nsfrb_multiscale_candidates_get(nsfrb_multiscale* h, nsfrb_scale_candidate* host_out,
                                              int32_t capacity, int32_t* n_written, int32_t* n_total);
 
+/* ----------------------------------------------------- PSF-based reduction
+ * Host-only post-processing of one image's top candidates (section 2.3): the
+ * simulated PSF host psf[psf_ny][psf_nx] (odd sides, centred on the middle
+ * pixel, centre > 0) is thresholded at `percentile` (0..100; the paper uses 90;
+ * linear interpolation between order statistics, as NumPy's default) into a
+ * binary mask (pixels >= the threshold). The mask is centred on each candidate
+ * in turn: the other candidates at offsets inside it are that candidate's
+ * possible sidelobes, and its score is the weighted mean S/N over itself
+ * (weight 1) and them (weight = PSF at the offset / PSF at the centre). Writes
+ * the index of the highest score (ties: the earlier candidate) and that score.
+ * INVALID_ARG for NULL pointers, n < 1, even sides, a non-finite PSF value, a
+ * centre <= 0 or a percentile outside 0..100. */
+nsfrb_status nsfrb_psf_reduce(const nsfrb_candidate* cands, int32_t n, const float* psf, int32_t psf_nx,
+                              int32_t psf_ny, double percentile, int32_t* best_index, double* best_score);
+
 /* ------------------------------------------------------------------ batch
  * Many cubes of uneven shape searched together (the process server of
  * section 2.2 batches search tasks per timescale). All configurations must

@@ -40,6 +40,7 @@ EXPORTS = [
     "nsfrb_classifier_train_step", "nsfrb_classifier_infer", "nsfrb_cutouts_extract",
     "nsfrb_bin_time", "nsfrb_multiscale_create", "nsfrb_multiscale_destroy", "nsfrb_multiscale_run",
     "nsfrb_multiscale_scale", "nsfrb_multiscale_candidates_get", "nsfrb_plan_dm_grid",
+    "nsfrb_psf_reduce",
 ]
 
 
@@ -155,6 +156,8 @@ def lib():
                                        ctypes.POINTER(CutoutDesc), i32, vp, vp], ctypes.c_int),
             "nsfrb_bin_time": ([vp, i32, i32, i32, i32, i32, vp, vp], ctypes.c_int),
             "nsfrb_plan_dm_grid": ([ctypes.c_double] * 8 + [pd, i32, pi32], ctypes.c_int),
+            "nsfrb_psf_reduce": ([ctypes.POINTER(Candidate), i32, pf, i32, i32, ctypes.c_double, pi32, pd],
+                                 ctypes.c_int),
             "nsfrb_multiscale_create": ([ctypes.POINTER(Config), i32, pi32, pd, ctypes.POINTER(vp)], ctypes.c_int),
             "nsfrb_multiscale_destroy": ([vp], ctypes.c_int),
             "nsfrb_multiscale_run": ([vp, vp, vp], ctypes.c_int),
@@ -252,6 +255,21 @@ def plan_dm_grid(nu_min_ghz, nu_max_ghz, chan_bw_mhz, t_s_ms, w_int_ms, tol, dm_
     out = np.zeros(n.value, np.float64)
     check(lib().nsfrb_plan_dm_grid(*args, _ptr(out, ctypes.c_double), n.value, ctypes.byref(n)))
     return out
+
+
+def psf_reduce(cands, psf, percentile=90.0):
+    """nsfrb_psf_reduce: index of the most likely candidate and its weighted mean S/N.
+    cands: dicts with x, y, snr (e.g. from Search.candidates) in list order."""
+    arr = (Candidate * len(cands))()
+    for i, c in enumerate(cands):
+        arr[i].x, arr[i].y, arr[i].snr = int(c["x"]), int(c["y"]), float(c["snr"])
+        arr[i].dm_index, arr[i].width_index, arr[i].toa = int(c.get("dm_index", 0)), int(c.get("width_index", 0)), \
+            int(c.get("toa", 0))
+    p = np.ascontiguousarray(psf, dtype=np.float32)
+    idx, score = ctypes.c_int32(), ctypes.c_double()
+    check(lib().nsfrb_psf_reduce(arr, len(cands), _ptr(p, ctypes.c_float), p.shape[1], p.shape[0], float(percentile),
+                                 ctypes.byref(idx), ctypes.byref(score)))
+    return idx.value, score.value
 
 
 def bin_time(d_x, in_dtype, n_time, n_sub, n_pix, factor, d_out, stream=0):

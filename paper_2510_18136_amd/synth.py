@@ -190,3 +190,26 @@ def philox_normals(n, seed, sigma=1.0):
     a1 = 2 * np.pi * u(w[:, 3])
     v = np.stack([r0 * np.cos(a0), r0 * np.sin(a0), r1 * np.cos(a1), r1 * np.sin(a1)], axis=1).reshape(-1)
     return sigma * v[:n]
+
+
+# ------------------------------------------------------------ simulated PSF
+def snapshot_psf(half=24, seed=11, n_ew=40, n_ns=16, lobe_px=0.6):
+    """Snapshot dirty beam of a T-shaped array (an east-west arm and a
+    north-south arm, as the DSA-110), on a (2 half + 1)^2 pixel grid centred on
+    the middle pixel: B(l, m) = sum over antenna pairs a != b of
+    cos(2 pi (u_ab l + v_ab m)) / (N (N - 1)), peak 1 at the centre, with
+    positive and negative sidelobes. Antennas sit at jittered, roughly even
+    spacings; the pixel scale puts the main lobe's half width near lobe_px."""
+    rng = np.random.default_rng(seed)
+    ew = np.sort(rng.uniform(-1.0, 1.0, n_ew))
+    ns = np.sort(rng.uniform(0.05, 1.0, n_ns))
+    x = np.concatenate([ew, np.zeros(n_ns)])
+    y = np.concatenate([np.zeros(n_ew), ns])
+    scale = 0.5 / (lobe_px * (x.max() - x.min()))          # cycles per pixel per unit baseline
+    g = np.arange(-half, half + 1) * scale
+    ph_x = np.exp(2j * np.pi * np.outer(x, g))              # [antenna][l]
+    ph_y = np.exp(2j * np.pi * np.outer(y, g))              # [antenna][m]
+    v = np.einsum("al,am->ml", ph_x, ph_y)                  # voltage sum [m][l]
+    n = x.size
+    beam = (np.abs(v) ** 2 - n) / (n * (n - 1))
+    return (beam / beam[half, half]).astype(np.float32)

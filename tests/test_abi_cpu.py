@@ -205,3 +205,29 @@ def test_dm_grid_truncation_reports_the_count(L):
     assert st == nsfrb.TRUNCATED and n.value == len(nsfrb.plan_dm_grid(1.311, 1.499, 11.71875, 134.2, 0.0, 1.6,
                                                                          0.0, 4000.0)) > 2
     assert out[0] == 0.0 and out[1] > 0.0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_psf_reduce_matches_oracle(L, seed):
+    from oracle import postproc
+    rng = np.random.default_rng(seed)
+    psf = synth.snapshot_psf(half=int(rng.integers(3, 16)), seed=seed)
+    n = int(rng.integers(1, 11))
+    cx, cy = 40, 40
+    cands = [dict(x=int(cx + rng.integers(-10, 11)), y=int(cy + rng.integers(-10, 11)),
+                  snr=float(np.float32(rng.uniform(6, 30)))) for _ in range(n)]
+    cands.sort(key=lambda c: -c["snr"])
+    i, s = nsfrb.psf_reduce(cands, psf, 90.0)
+    j, t = postproc.psf_reduce([(c["x"], c["y"], c["snr"]) for c in cands], psf, 90.0)
+    assert i == j and s == pytest.approx(t, rel=1e-12)
+
+
+def test_psf_reduce_hand_case_and_errors(L):
+    p = np.zeros((5, 5), np.float32)
+    p[2, 2], p[2, 4], p[2, 0], p[0, 2], p[4, 2] = 1.0, 0.5, 0.5, 0.25, 0.25
+    i, s = nsfrb.psf_reduce([dict(x=10, y=10, snr=8.0), dict(x=12, y=10, snr=6.0), dict(x=10, y=12, snr=7.0)], p)
+    assert i == 0 and s == pytest.approx(11.0 / 1.5)
+    for bad, pct in ((np.zeros((4, 5), np.float32), 90.0), (p, 120.0), (np.zeros((5, 5), np.float32), 90.0)):
+        with pytest.raises(nsfrb.NsfrbError) as e:
+            nsfrb.psf_reduce([dict(x=0, y=0, snr=7.0)], bad, pct)
+        assert e.value.status == nsfrb.INVALID_ARG
