@@ -346,7 +346,8 @@ def bench_psf(nsfrb, hip, synth, n_images=16):
     s = nsfrb.Search(cfg)
     buf = hip.Buffer(nt * ns * nx * ny * 4)
     rng = np.random.default_rng(77)
-    n_top, top1_ok, final_ok, final_near = [], 0, 0, 0
+    n_top, top1_ok, final_ok, final_near, final_lobe = [], 0, 0, 0, 0
+    q90 = float(np.percentile(psf, 90.0))
     for k in range(n_images):
         cube = synth.noise_cube(nt, ns, nx * ny, 500 + k)
         x0, y0 = int(rng.integers(12, 52)), int(rng.integers(12, 52))
@@ -370,12 +371,15 @@ def bench_psf(nsfrb, hip, synth, n_images=16):
         fx, fy = cands[i]["x"], cands[i]["y"]
         final_ok += (fx, fy) == (x0, y0)
         final_near += max(abs(fx - x0), abs(fy - y0)) <= 1
+        dx, dy = fx - x0, fy - y0
+        final_lobe += abs(dx) <= h and abs(dy) <= h and float(psf[h + dy, h + dx]) >= q90
     s.close()
     buf.close()
     return {"workload": f"{n_images} images of 64x64 px, 16 sub-bands, 256 samples; one pulse (S/N 10-30, DM "
                         "0-1000, width 4) convolved with a 63x63 simulated T-array snapshot beam; top 10 per image",
             "candidates_per_image_before": float(np.mean(n_top)), "candidates_per_image_after": 1.0,
             "final_is_source_pixel": final_ok / n_images, "final_within_1px": final_near / n_images,
+            "final_in_source_psf_mask": final_lobe / n_images,
             "top1_is_source_pixel": top1_ok / n_images}
 
 
