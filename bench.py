@@ -383,6 +383,28 @@ def bench_psf(nsfrb, hip, synth, n_images=16):
             "top1_is_source_pixel": top1_ok / n_images}
 
 
+def bench_stream(nsfrb, meta, x_ptr, n_t, n_searched=12):
+    """Real-time form at survey shape: 25-sample (3.35 s) batches into a ring of
+    the last 2048 samples, the window searched after every batch."""
+    chunk = 25
+    cfg = nsfrb.SearchConfig(meta["nx"], meta["ny"], n_t, meta["freqs"], meta["dms"], meta["widths"],
+                             snr_threshold=meta["theta"])
+    row = cfg.n_pix * cfg.n_sub * 4
+    s = nsfrb.Stream(cfg, chunk=chunk, deadline_ms=chunk * 134.2)
+    n_fill = (n_t + chunk - 1) // chunk
+    ms = []
+    for k in range(n_fill + n_searched):
+        off = (k * chunk) % (n_t - chunk + 1)          # batches cut from the survey cube
+        r = s.push(x_ptr + off * row, 0)
+        if r["searched"]:
+            ms.append(r["search_ms"])
+    s.close()
+    med = float(np.median(ms))
+    return {"workload": "survey shape, 25-sample (3.35 s) batches into a 2048-sample window, searched per batch",
+            "search_ms_per_batch": med, "batch_interval_ms": chunk * 134.2,
+            "realtime_margin": chunk * 134.2 / med, "searched_batches": len(ms)}
+
+
 def bench_tiny(nsfrb, hip, synth, reps=200):
     """Launch-bound tiny workload (32x32 px, 4 sub-bands, 64 samples, 8 DMs, widths 1-16):
     microseconds per complete run (statistics, search, candidates), back to back."""
@@ -417,6 +439,7 @@ def main():
     ap.add_argument("--no-paper-grid", action="store_true")
     ap.add_argument("--no-multiscale", action="store_true")
     ap.add_argument("--no-psf", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (counter calibration)")
     ap.add_argument("--traffic-from", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV",
@@ -545,6 +568,10 @@ def main():
             print(f"[bench] paper grid {store}: {m:.3f} ms/step, search {st[1]:.3f} ms "
                   f"({pg[store]['search_hbm_frac']:.2f} of HBM peak)", file=sys.stderr, flush=True)
         out["paper_grid"] = pg
+    if not args.no_stream:
+        out["stream"] = bench_stream(nsfrb, meta, x_ptr, cube.shape[0])
+        print(f"[bench] stream: {out['stream']['search_ms_per_batch']:.2f} ms per 3.35 s batch "
+              f"({out['stream']['realtime_margin']:.0f}x real time)", file=sys.stderr, flush=True)
     if not args.no_multiscale:
         out["multi_timescale"] = bench_multiscale(nsfrb, hip, synth, x_ptr, meta, cube.shape[0], args.steps,
                                                   args.warmup, ms)

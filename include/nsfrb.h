@@ -247,6 +247,43 @@ nsfrb_status nsfrb_multiscale_scale(nsfrb_multiscale* h, int32_t scale, nsfrb_se
 nsfrb_status nsfrb_multiscale_candidates_get(nsfrb_multiscale* h, nsfrb_scale_candidate* host_out,
                                              int32_t capacity, int32_t* n_written, int32_t* n_total);
 
+/* --------------------------------------------------------------- streaming
+ * Real-time form (section 2.2: images arrive continuously and are searched in
+ * fixed 3.35 s batches, 25 samples, under a timeout; the search reports one
+ * candidate per batch). The stream keeps the last n_time samples of the raw
+ * cube in a device ring (cfg: TSP layout, statistics computed by the search,
+ * not EXTERNAL) and, after each batch once the ring is full, searches the
+ * window it holds: robust statistics over the window, then the search of
+ * nsfrb_search_run. A search that takes longer than deadline_ms (measured with
+ * HIP events) makes the next iteration be dropped. A sub-band that did not
+ * arrive is passed as non-finite samples: its series are flagged and
+ * normalised to 0 (nsfrb_flag_count_get). */
+typedef struct nsfrb_stream nsfrb_stream; /* opaque handle */
+
+typedef struct {
+  int32_t searched;        /* 1 if this batch's window was searched              */
+  int32_t has_candidate;   /* 1 if a pixel reached the threshold                  */
+  nsfrb_candidate cand;    /* the window's best candidate (valid if has_candidate);
+                              its TOA is a sample index within the window        */
+  int64_t chunk_index;     /* batches pushed before this one                      */
+  int64_t window_start;    /* stream sample index of the window's first sample    */
+  float search_ms;         /* device time of the search (if searched)              */
+  int32_t dropped_total;   /* iterations dropped so far                             */
+  int64_t flagged;         /* series flagged in this window (if searched)          */
+} nsfrb_stream_result;
+
+/* chunk: samples per batch, 1..n_time; deadline_ms > 0. Errors as for
+ * nsfrb_search_create; UNSUPPORTED for a PST layout or EXTERNAL statistics. */
+nsfrb_status nsfrb_stream_create(const nsfrb_search_config* cfg, int32_t chunk, double deadline_ms,
+                                 nsfrb_stream** out);
+nsfrb_status nsfrb_stream_destroy(nsfrb_stream* s);
+/* Append one batch (device [chunk][n_sub][ny*nx] of in_dtype, copied into the
+ * ring on `stream`) and, when due, search the window; waits for the search and
+ * fills *out. */
+nsfrb_status nsfrb_stream_push(nsfrb_stream* s, const void* d_chunk, void* stream, nsfrb_stream_result* out);
+/* The stream's search handle (maps, statistics, z cube of the last searched window). */
+nsfrb_status nsfrb_stream_search(nsfrb_stream* s, nsfrb_search** out);
+
 /* ----------------------------------------------------- PSF-based reduction
  * Host-only post-processing of one image's top candidates (section 2.3): the
  * simulated PSF host psf[psf_ny][psf_nx] (odd sides, centred on the middle

@@ -597,7 +597,7 @@ __attribute__((amdgpu_waves_per_eu(StatShape<V>::kMinWavesPerEU))) void k_stats_
     const InT* __restrict__ x, int n_t, int n_sub, int n_pix, int mode,
     const double* __restrict__ med_in, const double* __restrict__ sig_in,
     double* __restrict__ med_out, double* __restrict__ sig_out,
-    ST* __restrict__ z, unsigned long long* __restrict__ flag_count) {
+    ST* __restrict__ z, unsigned long long* __restrict__ flag_count, int t_start) {
   constexpr int kStatWaves = StatShape<V>::kWaves;
   constexpr int kStatTilePix = kStatWaves;        // one pixel (series) per wave
   // each wave's series lives in LDS, sample t at row[t]; rows are padded so that
@@ -637,7 +637,9 @@ __attribute__((amdgpu_waves_per_eu(StatShape<V>::kMinWavesPerEU))) void k_stats_
   for (int q = 0; q < kPer; ++q) {
     const int t = q * kRowStep + r0;
     const bool ok = pix_ok && t < n_t;
-    const float v = to_f32(src[(size_t)(ok ? t : 0) * plane]);
+    int tr = t + t_start;                          // ring order: oldest sample first
+    tr -= tr >= n_t ? n_t : 0;
+    const float v = to_f32(src[(size_t)(ok ? tr : 0) * plane]);
     stage[q] = ok ? v : __builtin_nanf("");
   }
   float* my_row = series + c_ld * RS + r0;
@@ -657,7 +659,7 @@ static hipError_t launch_stats_v(const StatsLaunch& a, hipStream_t st) {
   dim3 grid((a.n_pix + W - 1) / W, a.n_sub);
   hipLaunchKernelGGL((k_stats_norm<V, InT, ST>), grid, dim3(W * kWave), 0, st,
                      (const InT*)a.x, a.n_t, a.n_sub, a.n_pix, a.mode, a.med_in, a.sig_in,
-                     a.med_out, a.sig_out, (ST*)a.z, a.flag_count);
+                     a.med_out, a.sig_out, (ST*)a.z, a.flag_count, a.t_start);
   return hipGetLastError();
 }
 

@@ -744,8 +744,16 @@ static nsfrb_status autotune(nsfrb_search* h, const std::vector<KernelClass>& ks
   return NSFRB_OK;
 }
 
+static nsfrb_status run_impl(nsfrb_search* h, const void* d_cube, int t_start, void* stream);
+
 extern "C" nsfrb_status nsfrb_search_run(nsfrb_search* h, const void* d_cube, void* stream) {
   g_last_error.clear();
+  return run_impl(h, d_cube, 0, stream);
+}
+
+// One search; d_cube is a raw TSP cube or, with t_start > 0, a ring of n_time
+// samples whose oldest sample is at time index t_start.
+static nsfrb_status run_impl(nsfrb_search* h, const void* d_cube, int t_start, void* stream) {
   if (!h || !d_cube) return fail(NSFRB_ERR_INVALID_ARG, "handle and d_cube must be non-NULL");
   if (h->cfg.norm == NSFRB_NORM_EXTERNAL && !h->ext_set)
     return fail(NSFRB_ERR_INVALID_ARG, "EXTERNAL normalisation needs nsfrb_noise_stats_set before run");
@@ -756,7 +764,7 @@ extern "C" nsfrb_status nsfrb_search_run(nsfrb_search* h, const void* d_cube, vo
   const void* z = d_cube;
   if (c.layout == NSFRB_LAYOUT_TSP) {
     StatsLaunch sa{d_cube, c.n_time, c.n_sub, h->n_pix, c.norm, c.in_dtype, c.store_dtype,
-                   h->d_ext_med, h->d_ext_sig, h->d_med, h->d_sig, h->d_z, h->d_flags};
+                   h->d_ext_med, h->d_ext_sig, h->d_med, h->d_sig, h->d_z, h->d_flags, t_start};
     HIP_TRY(launch_stats(sa, st));
     z = h->d_z;
   } else {
@@ -1320,5 +1328,134 @@ extern "C" nsfrb_status nsfrb_philox_fill(uint32_t* d_out, int64_t n_blocks, uin
   g_last_error.clear();
   if (!d_out || n_blocks < 0) return fail(NSFRB_ERR_INVALID_ARG, "bad arguments");
   HIP_TRY(launch_philox_fill(d_out, n_blocks, seed, (hipStream_t)stream));
+  return NSFRB_OK;
+}
+
+// --------------------------------------------------------------- streaming
+// Real-time form (section 2.2): images arrive in fixed batches of `chunk`
+// samples; the last n_time samples sit in a device ring (raw layout, one row
+// of n_sub x n_pix per sample) and are searched after each batch once the ring
+// is full; a search that overruns the deadline makes the next iteration be
+// dropped so the stream catches up.
+struct nsfrb_stream {
+  nsfrb_search* search = nullptr;
+  void* ring = nullptr;
+  size_t row_bytes = 0;
+  int n_time = 0, chunk = 0, head = 0;
+  int64_t received = 0, pushes = 0;
+  double deadline_ms = 0.0;
+  bool drop_next = false;
+  int32_t dropped = 0;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+};
+
+static void stream_release(nsfrb_stream* s) {
+  if (!s) return;
+  if (s->search) {
+    hipSetDevice(s->search->device);
+    nsfrb_search_destroy(s->search);
+  }
+  if (s->ring) hipFree(s->ring);
+  if (s->t0) hipEventDestroy(s->t0);
+  if (s->t1) hipEventDestroy(s->t1);
+  delete s;
+}
+
+extern "C" nsfrb_status nsfrb_stream_create(const nsfrb_search_config* cfg, int32_t chunk, double deadline_ms,
+                                            nsfrb_stream** out) {
+  g_last_error.clear();
+  if (!cfg || !out) return fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  nsfrb_status st = validate(cfg);
+  if (st != NSFRB_OK) return st;
+  if (cfg->layout != NSFRB_LAYOUT_TSP) return fail(NSFRB_ERR_UNSUPPORTED, "a stream takes raw [time][sub-band][pixel] batches");
+  if (cfg->norm == NSFRB_NORM_EXTERNAL) return fail(NSFRB_ERR_UNSUPPORTED, "a stream computes its own statistics");
+  if (chunk < 1 || chunk > cfg->n_time) return fail(NSFRB_ERR_INVALID_ARG, "chunk must be 1..n_time");
+  if (!(deadline_ms > 0.0) || !std::isfinite(deadline_ms)) return fail(NSFRB_ERR_INVALID_ARG, "deadline_ms must be > 0");
+  std::unique_ptr<nsfrb_stream, void (*)(nsfrb_stream*)> s(new nsfrb_stream, stream_release);
+  st = nsfrb_search_create(cfg, &s->search);
+  if (st != NSFRB_OK) return st;
+  s->n_time = cfg->n_time;
+  s->chunk = chunk;
+  s->deadline_ms = deadline_ms;
+  s->row_bytes = (size_t)cfg->n_sub * cfg->nx * cfg->ny * dtype_size(cfg->in_dtype);
+  HIP_TRY(hipSetDevice(cfg->device));
+  HIP_TRY(hipMalloc(&s->ring, s->row_bytes * cfg->n_time));
+  HIP_TRY(hipEventCreate(&s->t0));
+  HIP_TRY(hipEventCreate(&s->t1));
+  *out = s.release();
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_stream_destroy(nsfrb_stream* s) {
+  g_last_error.clear();
+  if (s && s->search) {
+    hipSetDevice(s->search->device);
+    hipDeviceSynchronize();
+  }
+  stream_release(s);
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_stream_push(nsfrb_stream* s, const void* d_chunk, void* stream,
+                                          nsfrb_stream_result* out) {
+  g_last_error.clear();
+  if (!s || !d_chunk || !out) return fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(s->search->device));
+  // append the batch at the ring's head (two copies when it wraps)
+  const int first = std::min(s->chunk, s->n_time - s->head);
+  HIP_TRY(hipMemcpyAsync((char*)s->ring + (size_t)s->head * s->row_bytes, d_chunk, (size_t)first * s->row_bytes,
+                         hipMemcpyDeviceToDevice, st));
+  if (first < s->chunk)
+    HIP_TRY(hipMemcpyAsync(s->ring, (const char*)d_chunk + (size_t)first * s->row_bytes,
+                           (size_t)(s->chunk - first) * s->row_bytes, hipMemcpyDeviceToDevice, st));
+  s->head = (s->head + s->chunk) % s->n_time;
+  s->received += s->chunk;
+  s->pushes += 1;
+  nsfrb_stream_result r{};
+  r.chunk_index = s->pushes - 1;
+  r.window_start = s->received - s->n_time;
+  r.dropped_total = s->dropped;
+  if (s->received < s->n_time) {             // the window is not full yet
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = r;
+    return NSFRB_OK;
+  }
+  if (s->drop_next) {                        // the previous search overran: skip this one
+    s->drop_next = false;
+    s->dropped += 1;
+    r.dropped_total = s->dropped;
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = r;
+    return NSFRB_OK;
+  }
+  HIP_TRY(hipEventRecord(s->t0, st));
+  nsfrb_status rs = run_impl(s->search, s->ring, s->head, stream);    // oldest sample at the head
+  if (rs != NSFRB_OK) return rs;
+  HIP_TRY(hipEventRecord(s->t1, st));
+  rs = wait_run(s->search);
+  if (rs != NSFRB_OK) return rs;
+  HIP_TRY(hipEventSynchronize(s->t1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, s->t0, s->t1));
+  r.searched = 1;
+  r.search_ms = ms;
+  if (ms > s->deadline_ms) s->drop_next = true;
+  unsigned long long flags = 0;
+  HIP_TRY(hipMemcpy(&flags, s->search->d_flags, sizeof(flags), hipMemcpyDeviceToHost));
+  r.flagged = (int64_t)flags;
+  if (s->search->h_nout[0] > 0) {            // one candidate per batch: the window's best
+    r.has_candidate = 1;
+    r.cand = s->search->h_cands[0];
+  }
+  *out = r;
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_stream_search(nsfrb_stream* s, nsfrb_search** out) {
+  g_last_error.clear();
+  if (!s || !out) return fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  *out = s->search;
   return NSFRB_OK;
 }

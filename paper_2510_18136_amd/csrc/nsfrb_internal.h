@@ -17,6 +17,7 @@ struct StatsLaunch {
   double* sig_out;
   void* z;
   unsigned long long* flag_count;
+  int t_start = 0;   // time index of the oldest sample when x is a ring of n_t samples (0: plain cube)
 };
 hipError_t launch_stats(const StatsLaunch& a, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t st);

@@ -40,7 +40,7 @@ EXPORTS = [
     "nsfrb_classifier_train_step", "nsfrb_classifier_infer", "nsfrb_cutouts_extract",
     "nsfrb_bin_time", "nsfrb_multiscale_create", "nsfrb_multiscale_destroy", "nsfrb_multiscale_run",
     "nsfrb_multiscale_scale", "nsfrb_multiscale_candidates_get", "nsfrb_plan_dm_grid",
-    "nsfrb_psf_reduce",
+    "nsfrb_psf_reduce", "nsfrb_stream_create", "nsfrb_stream_destroy", "nsfrb_stream_push", "nsfrb_stream_search",
 ]
 
 
@@ -66,6 +66,12 @@ class Candidate(ctypes.Structure):
 
 class ScaleCandidate(ctypes.Structure):
     _fields_ = [("cand", Candidate), ("scale", ctypes.c_int32)]
+
+
+class StreamResult(ctypes.Structure):
+    _fields_ = [("searched", ctypes.c_int32), ("has_candidate", ctypes.c_int32), ("cand", Candidate),
+                ("chunk_index", ctypes.c_int64), ("window_start", ctypes.c_int64), ("search_ms", ctypes.c_float),
+                ("dropped_total", ctypes.c_int32), ("flagged", ctypes.c_int64)]
 
 
 class ClassifierConfig(ctypes.Structure):
@@ -158,6 +164,10 @@ def lib():
             "nsfrb_plan_dm_grid": ([ctypes.c_double] * 8 + [pd, i32, pi32], ctypes.c_int),
             "nsfrb_psf_reduce": ([ctypes.POINTER(Candidate), i32, pf, i32, i32, ctypes.c_double, pi32, pd],
                                  ctypes.c_int),
+            "nsfrb_stream_create": ([ctypes.POINTER(Config), i32, ctypes.c_double, ctypes.POINTER(vp)], ctypes.c_int),
+            "nsfrb_stream_destroy": ([vp], ctypes.c_int),
+            "nsfrb_stream_push": ([vp, vp, vp, ctypes.POINTER(StreamResult)], ctypes.c_int),
+            "nsfrb_stream_search": ([vp, ctypes.POINTER(vp)], ctypes.c_int),
             "nsfrb_multiscale_create": ([ctypes.POINTER(Config), i32, pi32, pd, ctypes.POINTER(vp)], ctypes.c_int),
             "nsfrb_multiscale_destroy": ([vp], ctypes.c_int),
             "nsfrb_multiscale_run": ([vp, vp, vp], ctypes.c_int),
@@ -336,6 +346,50 @@ class MultiScale:
         recs = [dict(x=r.cand.x, y=r.cand.y, dm_index=r.cand.dm_index, width_index=r.cand.width_index,
                      toa=r.cand.toa, snr=r.cand.snr, scale=r.scale) for r in arr[:nw.value]]
         return recs, nt.value, st
+
+
+class Stream:
+    """Real-time form (nsfrb_stream_*): batches of `chunk` samples into a ring of
+    cfg.n_time samples, the window searched after each batch once full."""
+
+    def __init__(self, cfg: SearchConfig, chunk=25, deadline_ms=3350.0):
+        h = ctypes.c_void_p()
+        check(lib().nsfrb_stream_create(ctypes.byref(cfg.c), int(chunk), float(deadline_ms), ctypes.byref(h)))
+        self.h, self.cfg, self.chunk = h, cfg, int(chunk)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nsfrb_stream_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def push(self, d_chunk_ptr, stream=0):
+        r = StreamResult()
+        check(lib().nsfrb_stream_push(self.h, ctypes.c_void_p(int(d_chunk_ptr)), ctypes.c_void_p(int(stream)),
+                                      ctypes.byref(r)))
+        c = r.cand
+        return dict(searched=bool(r.searched), has_candidate=bool(r.has_candidate), chunk_index=r.chunk_index,
+                    window_start=r.window_start, search_ms=r.search_ms, dropped_total=r.dropped_total,
+                    flagged=r.flagged,
+                    cand=dict(x=c.x, y=c.y, dm_index=c.dm_index, width_index=c.width_index, toa=c.toa, snr=c.snr)
+                    if r.has_candidate else None)
+
+    def search(self):
+        """Search view of the last searched window (maps, statistics, z cube)."""
+        p = ctypes.c_void_p()
+        check(lib().nsfrb_stream_search(self.h, ctypes.byref(p)))
+        return Search._borrow(self.cfg, p, self)
 
 
 class Search:

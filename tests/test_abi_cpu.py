@@ -231,3 +231,16 @@ def test_psf_reduce_hand_case_and_errors(L):
         with pytest.raises(nsfrb.NsfrbError) as e:
             nsfrb.psf_reduce([dict(x=0, y=0, snr=7.0)], bad, pct)
         assert e.value.status == nsfrb.INVALID_ARG
+
+
+@pytest.mark.parametrize("kw,chunk,deadline,status", [
+    ({}, 0, 100.0, nsfrb.INVALID_ARG),
+    ({}, 4097, 100.0, nsfrb.INVALID_ARG),
+    ({}, 25, 0.0, nsfrb.INVALID_ARG),
+    (dict(layout="pst", norm="none", in_dtype="f16", store_dtype="f16"), 25, 100.0, nsfrb.UNSUPPORTED),
+    (dict(norm="external"), 25, 100.0, nsfrb.UNSUPPORTED),
+])
+def test_stream_rejects_bad_plans_before_the_gpu(L, kw, chunk, deadline, status):
+    with pytest.raises(nsfrb.NsfrbError) as e:
+        nsfrb.Stream(c2_config(**kw), chunk=chunk, deadline_ms=deadline)
+    assert e.value.status == status

@@ -1,0 +1,102 @@
+"""GPU parity of the real-time (streaming) form (needs an MI355X).
+
+Batches of 25 samples go into a ring of the last n_time samples; after each
+batch, once the ring is full, the window is searched. Each searched window is
+compared with the oracle's search of the same trailing samples (statistics and
+normalised cube bit-exact, the reported candidate = the oracle's best, S/N within
+1e-4). Also: a sub-band that did not arrive (non-finite samples) is flagged in
+every window that holds it and the search goes on; a deadline the search cannot
+meet drops every other iteration.
+"""
+import numpy as np
+import pytest
+
+from oracle import search as osr
+from paper_2510_18136_amd import nsfrb, synth
+from tests._lib import ensure_built
+from tests.test_gpu_search import EPS, TOL
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NX, NY, NS, NT, CHUNK = 16, 8, 4, 100, 25
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    ensure_built()
+    assert torch.cuda.is_available()
+
+
+def make_stream(seed, n_chunks):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n_chunks * CHUNK, NS, NX * NY)).astype(np.float32)
+    for k, (p, t0, w, a) in enumerate([(5, 60, 3, 2.5), (77, 170, 8, 1.6), (100, 230, 2, 3.0)]):
+        off = synth.arrival_offsets(300.0 * k, synth.C1_FREQS, synth.C1_FREQS.max(), synth.DT_MS)
+        synth.inject_boxcar(x, p, t0, off, w, a)
+    return x
+
+
+def cfg():
+    return nsfrb.SearchConfig(NX, NY, NT, synth.C1_FREQS, np.linspace(0, 1000, 8), [1, 2, 4, 8], snr_threshold=4.0,
+                              max_candidates=10)
+
+
+def test_windows_match_oracle():
+    n_chunks = 12
+    x = make_stream(3, n_chunks)
+    xd = torch.from_numpy(x).cuda()
+    c = cfg()
+    with nsfrb.Stream(c, chunk=CHUNK, deadline_ms=1e6) as s:
+        for k in range(n_chunks):
+            print(f"[gpu] stream push {k}", flush=True)
+            r = s.push(xd[k * CHUNK:(k + 1) * CHUNK].data_ptr(), torch.cuda.current_stream().cuda_stream)
+            received = (k + 1) * CHUNK
+            assert r["chunk_index"] == k and r["window_start"] == received - NT
+            if received < NT:
+                assert not r["searched"]
+                continue
+            assert r["searched"] and r["dropped_total"] == 0
+            win = x[received - NT:received]
+            o = osr.search(win, c.freqs, float(c.c.f_ref_ghz), c.c.dt_ms, c.dms, list(c.widths), NX, theta=4.0,
+                           k_max=10)
+            v = s.search()
+            np.testing.assert_array_equal(v.zcube()[0], np.transpose(o["z"], (2, 1, 0)))
+            med, sig = v.noise_stats()
+            np.testing.assert_array_equal(med, o["med"])
+            np.testing.assert_array_equal(sig, o["sigma"])
+            assert r["has_candidate"] == (o["n_total"] > 0)
+            if o["n_total"]:
+                oc = o["candidates"]
+                assert abs(r["cand"]["snr"] - oc[0]["snr"]) <= TOL
+                if len(oc) == 1 or oc[0]["snr"] - oc[1]["snr"] > EPS:
+                    assert (r["cand"]["x"], r["cand"]["y"]) == (oc[0]["x"], oc[0]["y"])
+
+
+def test_missing_sub_band_is_flagged_and_the_search_goes_on():
+    n_chunks = 10
+    x = make_stream(4, n_chunks)
+    x[5 * CHUNK:6 * CHUNK, 2, :] = np.nan                 # batch 5: sub-band 2 never arrived
+    xd = torch.from_numpy(x).cuda()
+    with nsfrb.Stream(cfg(), chunk=CHUNK, deadline_ms=1e6) as s:
+        for k in range(n_chunks):
+            print(f"[gpu] stream push {k} (missing sub-band)", flush=True)
+            r = s.push(xd[k * CHUNK:(k + 1) * CHUNK].data_ptr(), torch.cuda.current_stream().cuda_stream)
+            if not r["searched"]:
+                continue
+            holds = (k + 1) * CHUNK - NT <= 5 * CHUNK < (k + 1) * CHUNK
+            assert r["flagged"] == (NX * NY if holds else 0)
+
+
+def test_deadline_drops_every_other_iteration():
+    n_chunks = 10
+    x = make_stream(5, n_chunks)
+    xd = torch.from_numpy(x).cuda()
+    searched = []
+    with nsfrb.Stream(cfg(), chunk=CHUNK, deadline_ms=1e-6) as s:
+        for k in range(n_chunks):
+            print(f"[gpu] stream push {k} (deadline)", flush=True)
+            r = s.push(xd[k * CHUNK:(k + 1) * CHUNK].data_ptr(), torch.cuda.current_stream().cuda_stream)
+            if (k + 1) * CHUNK >= NT:
+                searched.append(r["searched"])
+    assert searched == [True, False] * (len(searched) // 2) + [True] * (len(searched) % 2)
