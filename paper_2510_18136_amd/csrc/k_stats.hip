@@ -8,11 +8,11 @@
 // because wide pulses bias a plain one).
 //
 // Launch: one workgroup of W waves per (tile of W pixels, sub-band), W = 16
-// (8 for series longer than 1024 samples). The
-// raw cube [t][s][p] is read in coalesced W-pixel rows and transposed through
-// LDS so that each wave holds one pixel's series in registers (lane l, register
-// j <-> sample t = 64 j + l). The z series is written time-contiguous to the
-// search layout [p][s][t].
+// (8 for series longer than 1024 samples). The raw cube [t][s][p] (or a ring
+// of its last n_t samples, read oldest first) is loaded in coalesced W-pixel
+// rows into one padded LDS row per pixel; wave w works on pixel w's row, lane l
+// and step j reading sample t = 64 j + l. The z series is written
+// time-contiguous to the search layout [p][s][t].
 //
 // Exact selection: an order statistic of FP32 keys is found by adaptive
 // histogramming over [lo, hi] into 256 equal bins (bin = floor((v - lo) *
@@ -71,12 +71,7 @@ struct Sel {
 };
 
 // Keys of a series seen through an accessor key(j), j = 0..V-1 (sample
-// 64 j + lane): FP32 registers, or the series itself in LDS.
-template <int V>
-struct RegKeys {
-  const float (&a)[V];
-  __device__ __forceinline__ float operator()(int j) const { return a[j]; }
-};
+// 64 j + lane): the series itself in LDS, or a value derived from it.
 struct LdsSeries {
   const float* x;     // this wave's series, sample t at x[t]
   int l;
