@@ -1,5 +1,8 @@
 """GPU parity of the HIP search against the FP64 oracle (needs an MI355X).
 
+Sizes: from tiny and ragged shapes through the library's maxima to the full
+survey shape (sampled pixels, checked one by one).
+
 Rules (the oracle and the HIP path share no code; inputs are seeded):
   * delay table, noise statistics and the normalised cube: bit-exact;
   * S/N maps: |GPU - oracle| <= 1e-4 (FP32 store);
@@ -330,3 +333,48 @@ def test_deterministic_runs():
     for k in ("snr", "toa", "best", "best_d", "best_w", "best_t", "z", "med", "sig"):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
     assert a["cands"] == b["cands"]
+
+
+# Full survey shape (256x256 px, 16 sub-bands, 2048 samples, 32 DMs, 12 widths up to
+# 1200), in the plans bench.py times: the oracle checks a sample of pixels one by one
+# (every injected pulse plus random ones; pixels are independent), and the candidate
+# list is checked against the GPU's own best map (sorted top-K, total count).
+@pytest.mark.parametrize("store", ["f32", "f16"])
+def test_survey_shape_sampled_parity(store):
+    cube, meta = synth.config2(seed=2)
+    cfg = nsfrb.SearchConfig(meta["nx"], meta["ny"], cube.shape[0], meta["freqs"], meta["dms"], meta["widths"],
+                             store_dtype=store, snr_threshold=meta["theta"], max_candidates=10)
+    x = torch.from_numpy(cube).cuda()
+    with nsfrb.Search(cfg) as s:
+        print(f"[gpu] survey-shape search store={store} plan={s.plan_info()}", flush=True)
+        s.run(x.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        cands, n_total, _ = s.candidates()
+        snr, toa = s.maps()
+        bs, bd, bw, bt = s.best()
+        med, sig = s.noise_stats()
+    del x
+    rng = np.random.default_rng(12)
+    pix = np.unique(np.concatenate([[j["p"] for j in meta["injections"]], rng.choice(cfg.n_pix, 60, replace=False)]))
+    sub = np.ascontiguousarray(cube[:, :, pix])
+    o = osr.search(sub, cfg.freqs, float(cfg.c.f_ref_ghz), cfg.c.dt_ms, cfg.dms, list(cfg.widths), len(pix),
+                   store=store, theta=meta["theta"], k_max=10)
+    _, _, margin = osr.snr_toa_margin_maps(o["z"], o["delays"], list(cfg.widths))
+    tol = TOL if store == "f32" else 2e-4
+    np.testing.assert_array_equal(med[pix], o["med"])
+    np.testing.assert_array_equal(sig[pix], o["sigma"])
+    g = snr[:, :, pix]
+    fin = np.isfinite(o["snr_max"])
+    assert np.array_equal(np.isfinite(g), fin)
+    assert np.abs(g[fin] - o["snr_max"][fin]).max() <= tol
+    clear = fin & (margin > EPS)
+    np.testing.assert_array_equal(toa[:, :, pix][clear], o["toa"][clear])
+    assert np.abs(bs[pix] - o["best"]).max() <= tol
+    ok = dw_margin(o["snr_max"]) > EPS
+    np.testing.assert_array_equal(bd[pix][ok], o["best_d"][ok])
+    np.testing.assert_array_equal(bw[pix][ok], o["best_w"][ok])
+    # candidates: the GPU's own best map, thresholded, sorted by (-S/N, pixel), first K
+    above = np.flatnonzero(bs >= meta["theta"])
+    assert n_total == above.size
+    order = sorted(above.tolist(), key=lambda p: (-float(bs[p]), p))[:10]
+    assert [c["y"] * cfg.nx + c["x"] for c in cands] == order
+    assert all(c["snr"] == bs[c["y"] * cfg.nx + c["x"]] for c in cands)
