@@ -173,22 +173,8 @@ def cpu_baseline(cube, meta, target_s=12.0):
                       f"12 widths), {elapsed:.2f} s of NumPy FP64 on one thread"}
 
 
-def batch_shapes(seed=4, n=64, cap_bytes=128e9):
-    """Cube shapes of the batched workload: side log-uniform 64-512, samples
-    log-uniform 256-4096, sub-bands 8 or 16; redrawn with seed + 1 until the
-    FP16 total fits the cap."""
-    while True:
-        rng = np.random.default_rng(seed)
-        side = np.rint(np.exp(rng.uniform(np.log(64), np.log(512), n))).astype(int)
-        nt = np.rint(np.exp(rng.uniform(np.log(256), np.log(4096), n))).astype(int)
-        ns = rng.choice([8, 16], n)
-        total = float(np.sum(side * side * ns * nt * 2))
-        if total <= cap_bytes:
-            return [(int(a), int(b), int(c)) for a, b, c in zip(side, ns, nt)], total, seed
-        seed += 1
-
-
 def bench_batch(nsfrb, hip, reps=3):
+    from paper_2510_18136_amd.synth import batch_shapes
     shapes, total, seed = batch_shapes()
     dms, widths = np.linspace(0.0, 1000.0, 8), [1, 2, 4, 8, 16]
     t0 = time.time()

@@ -213,3 +213,18 @@ def snapshot_psf(half=24, seed=11, n_ew=40, n_ns=16, lobe_px=0.6):
     n = x.size
     beam = (np.abs(v) ** 2 - n) / (n * (n - 1))
     return (beam / beam[half, half]).astype(np.float32)
+
+
+def batch_shapes(seed=4, n=64, cap_bytes=128e9):
+    """Cube shapes (side, sub-bands, samples) of the batched workload: side
+    log-uniform 64-512, samples log-uniform 256-4096, sub-bands 8 or 16; redrawn
+    with seed + 1 until the FP16 total fits the cap. Returns (shapes, bytes, seed)."""
+    while True:
+        rng = np.random.default_rng(seed)
+        side = np.rint(np.exp(rng.uniform(np.log(64), np.log(512), n))).astype(int)
+        nt = np.rint(np.exp(rng.uniform(np.log(256), np.log(4096), n))).astype(int)
+        ns = rng.choice([8, 16], n)
+        total = float(np.sum(side * side * ns * nt * 2))
+        if total <= cap_bytes:
+            return [(int(a), int(b), int(c)) for a, b, c in zip(side, ns, nt)], total, seed
+        seed += 1

@@ -3,6 +3,8 @@
 * the persistent, graph-captured batch gives results bitwise equal to one plain
   launch per cube, on every graph replay (with eager work in between);
 * on small host-generated cubes the batch matches the FP64 oracle;
+* at the benchmarked size (64 uneven cubes, ~108 GB) graph replay equals plain
+  launches bit for bit, and the smallest cube matches the oracle in full;
 * the device Philox4x32-10 words equal the host implementation bit for bit,
   and its Box-Muller normals agree with an FP64 evaluation.
 """
@@ -174,3 +176,42 @@ def test_inject_boxcars_rejects_shared_pixels():
     with pytest.raises(nsfrb.NsfrbError):
         nsfrb.inject_boxcars([cube.data_ptr()], "f32", "tsp", 4, 2, 8, [(0, 1, 0, 1, 1.0), (0, 1, 3, 1, 1.0)],
                              np.zeros((2, 2), np.int32))
+
+
+def test_full_size_batch_graph_equals_separate_and_oracle():
+    """The benchmarked batch (64 uneven FP16 cubes, ~108 GB, sides 64-512, 256-4096
+    samples): every cube's maps and candidates from the graph replay equal those of
+    one plain launch per cube, bit for bit; the smallest cube, copied back from the
+    device, is checked against the oracle in full."""
+    shapes, total, _ = synth.batch_shapes()
+    widths = [1, 2, 4, 8, 16]
+    stream = torch.cuda.current_stream().cuda_stream
+    cfgs, cubes = [], []
+    for k, (side, ns, nt) in enumerate(shapes):
+        c = nsfrb.SearchConfig(side, side, nt, np.linspace(1.311, 1.499, ns), C1_DMS, widths, in_dtype="f16",
+                               store_dtype="f16", norm="none", layout="pst", snr_threshold=6.0)
+        x = torch.empty(side * side * ns * nt, dtype=torch.float16, device="cuda")
+        nsfrb.generate_noise(x.data_ptr(), "f16", "pst", side * side, ns, nt, 1000 + k, stream=stream)
+        off = delay_table(c.freqs, c.freqs.max(), 134.2, [500.0])[0]
+        nsfrb.inject_boxcar(x.data_ptr(), "f16", "pst", side * side, ns, nt, pixel=(side // 2) * side + side // 2,
+                            t0=min(20, nt - 8), width=4, amp=1.0, offsets=off, stream=stream)
+        cfgs.append(c)
+        cubes.append(x)
+    ptrs = [x.data_ptr() for x in cubes]
+    print(f"[gpu] full-size batch: {len(cfgs)} cubes, {total / 1e9:.1f} GB", flush=True)
+    with nsfrb.Batch(cfgs) as b:
+        b.run(ptrs, stream)
+        got = results(b, len(cfgs))
+        assert b.info()["graph"]
+        b.run_separate(ptrs, stream)
+        same(got, results(b, len(cfgs)))
+    k = int(np.argmin([s * s * ns * nt for s, ns, nt in shapes]))
+    c = cfgs[k]
+    z = cubes[k].cpu().numpy().astype(np.float32).reshape(c.n_pix, c.n_sub, c.n_time)   # [p][s][t]
+    o = oracle_run(np.transpose(z, (2, 1, 0)).copy(), c)
+    snr, toa, cands, ntot = got[k]
+    fin = np.isfinite(o["snr_max"])
+    assert np.array_equal(np.isfinite(snr), fin)
+    assert np.abs(snr[fin] - o["snr_max"][fin]).max() <= 2e-4
+    clear = fin & (o["margin"] > 2e-4)
+    np.testing.assert_array_equal(toa[clear], o["toa"][clear])
