@@ -40,7 +40,7 @@ extern "C" {
 typedef enum {
   NSFRB_OK = 0,
   NSFRB_ERR_INVALID_ARG = 1,   /* a value violates the documented domain        */
-  NSFRB_ERR_UNSUPPORTED = 2,   /* valid, but beyond what this build implements  */
+  NSFRB_ERR_UNSUPPORTED = 2,   /* valid, but beyond what the library implements */
   NSFRB_ERR_OUT_OF_MEMORY = 3, /* a device or pinned-host allocation failed     */
   NSFRB_ERR_DEVICE = 4,        /* a HIP runtime or kernel error                  */
   NSFRB_ERR_NOT_READY = 5,     /* results requested before any run              */

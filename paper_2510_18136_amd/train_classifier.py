@@ -309,7 +309,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--out", default="gpurun_out/classifier")
+    ap.add_argument("--out", default="classifier_run")
     a = ap.parse_args(argv)
     _torch()                     # torch's HIP runtime first, then the library (one runtime per process)
     os.makedirs(a.out, exist_ok=True)
