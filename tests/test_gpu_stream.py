@@ -14,7 +14,7 @@ import pytest
 from oracle import search as osr
 from paper_2510_18136_amd import nsfrb, synth
 from tests._lib import ensure_built
-from tests.test_gpu_search import EPS, TOL
+from tests.test_gpu_search import EPS, TOL, dw_margin
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -100,3 +100,61 @@ def test_deadline_drops_every_other_iteration():
             if (k + 1) * CHUNK >= NT:
                 searched.append(r["searched"])
     assert searched == [True, False] * (len(searched) // 2) + [True] * (len(searched) % 2)
+
+
+def test_survey_shape_wrapped_windows_sampled_parity():
+    """The survey shape (256x256 px, 16 sub-bands, 2048-sample window, 32 DMs,
+    12 widths, FP32) streamed in 25-sample batches: the window fills with the
+    82nd batch, when the ring has already wrapped, so every searched window
+    starts at a ring offset (2, 27, 52, 77). For each, sampled pixels (every
+    injected pulse and 50 random ones) are checked against the oracle's search
+    of the same trailing samples: statistics bit-exact, S/N maps and best trials
+    within 1e-4, TOA and best trial indices where they are unique; the reported
+    candidate is the maximum of the GPU's own best map."""
+    nb = 85
+    cube, meta = synth.config2(seed=6, nt=nb * CHUNK)
+    nt = 2048
+    c = nsfrb.SearchConfig(meta["nx"], meta["ny"], nt, meta["freqs"], meta["dms"], meta["widths"],
+                           snr_threshold=meta["theta"], max_candidates=10)
+    theta = meta["theta"]
+    x = torch.from_numpy(cube).cuda()
+    rng = np.random.default_rng(21)
+    checked = 0
+    with nsfrb.Stream(c, chunk=CHUNK, deadline_ms=1e6) as s:
+        for k in range(nb):
+            r = s.push(x[k * CHUNK:(k + 1) * CHUNK].data_ptr(), torch.cuda.current_stream().cuda_stream)
+            received = (k + 1) * CHUNK
+            if received < nt:
+                assert not r["searched"]
+                continue
+            print(f"[gpu] survey stream window start={received - nt}", flush=True)
+            assert r["searched"] and r["window_start"] == received - nt and r["dropped_total"] == 0
+            v = s.search()
+            snr, toa = v.maps()
+            bs, bd, bw, _ = v.best()
+            med, sig = v.noise_stats()
+            pix = np.unique(np.concatenate([[j["p"] for j in meta["injections"]],
+                                            rng.choice(c.n_pix, 50, replace=False)]))
+            sub = np.ascontiguousarray(cube[received - nt:received][:, :, pix])
+            o = osr.search(sub, c.freqs, float(c.c.f_ref_ghz), c.c.dt_ms, c.dms, list(c.widths), len(pix),
+                           theta=theta, k_max=10)
+            _, _, margin = osr.snr_toa_margin_maps(o["z"], o["delays"], list(c.widths))
+            np.testing.assert_array_equal(med[pix], o["med"])
+            np.testing.assert_array_equal(sig[pix], o["sigma"])
+            g = snr[:, :, pix]
+            fin = np.isfinite(o["snr_max"])
+            assert np.array_equal(np.isfinite(g), fin)
+            assert np.abs(g[fin] - o["snr_max"][fin]).max() <= TOL
+            clear = fin & (margin > EPS)
+            np.testing.assert_array_equal(toa[:, :, pix][clear], o["toa"][clear])
+            assert np.abs(bs[pix] - o["best"]).max() <= TOL
+            ok = dw_margin(o["snr_max"]) > EPS
+            np.testing.assert_array_equal(bd[pix][ok], o["best_d"][ok])
+            np.testing.assert_array_equal(bw[pix][ok], o["best_w"][ok])
+            assert r["has_candidate"] == bool((bs >= theta).any())
+            if r["has_candidate"]:
+                top = int(np.argmax(bs))
+                assert r["cand"]["snr"] == bs[top]
+                assert (r["cand"]["x"], r["cand"]["y"]) == (top % c.nx, top // c.nx)
+            checked += 1
+    assert checked == nb - nt // CHUNK
