@@ -309,6 +309,22 @@ def test_nan_input_is_flagged():
     compare(g, o, cfg)
 
 
+@pytest.mark.parametrize("nx,ny,ns,nt", [(1, 1, 1, 1), (2, 1, 2, 64)])
+def test_degenerate_shapes(nx, ny, ns, nt):
+    """The smallest plan (one pixel, one sub-band, one sample, DM 0, width 1),
+    whose only series has MAD 0 and is flagged; and a sub-band held constant in
+    one pixel (MAD 0, flagged) beside normal series."""
+    rng = np.random.default_rng(nt)
+    cube = rng.standard_normal((nt, ns, nx * ny)).astype(np.float32)
+    if nt > 1:
+        cube[:, 0, 0] = 2.5
+    freqs = np.linspace(1.3, 1.5, ns) if ns > 1 else np.array([1.4])
+    cfg = nsfrb.SearchConfig(nx, ny, nt, freqs, np.array([0.0]), [1], snr_threshold=3.0, max_candidates=4)
+    g, o = run_gpu(cube, cfg), oracle_run(cube, cfg)
+    assert g["flags"] == 1
+    compare(g, o, cfg)
+
+
 def test_truncation_and_not_ready():
     cube, meta = synth.config1(amp=6.0)
     cfg = c1_cfg(snr_threshold=3.0, max_candidates=8)
