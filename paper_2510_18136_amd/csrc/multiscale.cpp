@@ -131,14 +131,31 @@ extern "C" nsfrb_status nsfrb_multiscale_run(nsfrb_multiscale* h, const void* d_
   host_clear_error();
   if (!h || !d_cube) return host_fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
   NSFRB_HIP_TRY(hipSetDevice(h->base.device));
-  for (size_t s = 0; s < h->search.size(); ++s) {
-    const void* src = d_cube;
-    if (h->factor[s] > 1) {
+  // Bin first: two timescales whose factors nest (5 and 75) are binned from one
+  // read of the raw cube; any other binned timescale on its own.
+  const size_t n = h->search.size();
+  std::vector<bool> binned(n, false);
+  for (size_t s = 0; s < n; ++s) {
+    if (h->factor[s] <= 1 || binned[s]) continue;
+    size_t pair = n;
+    for (size_t q = s + 1; q < n && pair == n; ++q) {
+      const int32_t lo = std::min(h->factor[s], h->factor[q]), hi = std::max(h->factor[s], h->factor[q]);
+      if (!binned[q] && lo > 1 && hi > lo && hi % lo == 0) pair = q;
+    }
+    if (pair == n) {
       NSFRB_HIP_TRY(launch_bin_time(d_cube, h->base.in_dtype, h->base.n_time, h->base.n_sub, h->n_pix, h->factor[s],
                                     h->binned[s], (hipStream_t)stream));
-      src = h->binned[s];
+    } else {
+      const size_t a = h->factor[s] < h->factor[pair] ? s : pair, b = a == s ? pair : s;
+      NSFRB_HIP_TRY(launch_bin_time_pair(d_cube, h->base.in_dtype, h->base.n_time, h->base.n_sub, h->n_pix,
+                                         h->factor[a], h->binned[a], h->factor[b], h->binned[b],
+                                         (hipStream_t)stream));
+      binned[pair] = true;
     }
-    nsfrb_status st = nsfrb_search_run(h->search[s], src, stream);
+    binned[s] = true;
+  }
+  for (size_t s = 0; s < n; ++s) {
+    nsfrb_status st = nsfrb_search_run(h->search[s], h->factor[s] > 1 ? h->binned[s] : d_cube, stream);
     if (st != NSFRB_OK) return st;
   }
   return NSFRB_OK;

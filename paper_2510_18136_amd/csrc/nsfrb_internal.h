@@ -75,6 +75,10 @@ struct BoxcarRec {
 // out[t'][s][p] = RN32(FP64 sum of x[t' factor + k][s][p], k = 0..factor-1 in order), t' < n_t / factor
 hipError_t launch_bin_time(const void* x, int in_dtype, int n_t, int n_sub, int n_pix, int factor, float* out,
                            hipStream_t st);
+// Both binnings of launch_bin_time for factors fa and fb (fa >= 2, fb a larger multiple of fa) from one read
+// of x; outputs equal two launch_bin_time calls. hipErrorInvalidValue if the factors do not nest.
+hipError_t launch_bin_time_pair(const void* x, int in_dtype, int n_t, int n_sub, int n_pix, int fa, float* out_a,
+                                int fb, float* out_b, hipStream_t st);
 hipError_t launch_inject_many(void* const* cubes, int dtype, int layout, int n_pix, int n_sub, int n_t,
                               const BoxcarRec* recs, const int* offsets, int n, hipStream_t st);
 hipError_t launch_inject_rfi(void* cube, int dtype, int layout, int n_pix, int n_sub, int n_t, int kind, int t0, int len,

@@ -73,15 +73,19 @@ def test_bin_time_bit_exact(in_dtype):
         np.testing.assert_array_equal(out.cpu().numpy(), osr.bin_time(vals, f))
 
 
-@pytest.mark.parametrize("store,nt", [("f32", 600), ("f16", 751), ("bf16", 375)])
-def test_multiscale_matches_oracle(store, nt):
+@pytest.mark.parametrize("store,nt,in_dtype", [("f32", 600, "f32"), ("f16", 751, "f32"), ("bf16", 375, "f32"),
+                                               ("f32", 1210, "f16"), ("f16", 908, "bf16")])
+def test_multiscale_matches_oracle(store, nt, in_dtype):
+    """1210 and 908 samples leave 2 and 1 trailing 5-sample bins past the last
+    whole 75-sample bin, so the one-read binning of both factors has a partial
+    last group."""
     nx, ny, ns = 16, 8, 8
     cube, freqs = make_cube(31 + nt, nt, ns, nx * ny)
     cfg = nsfrb.SearchConfig(nx, ny, nt, freqs, np.linspace(0, 1000, 6), [1, 2, 4, 8, 16], store_dtype=store,
-                             snr_threshold=4.0, max_candidates=25)
-    xd = to_device(cube, "f32")
+                             in_dtype=in_dtype, snr_threshold=4.0, max_candidates=25)
+    xd = to_device(cube, in_dtype)
     with nsfrb.MultiScale(cfg, FACTORS, DM_SCALES) as ms:
-        print(f"[gpu] multiscale store={store} nt={nt}", flush=True)
+        print(f"[gpu] multiscale store={store} nt={nt} in={in_dtype}", flush=True)
         ms.run(xd.data_ptr(), torch.cuda.current_stream().cuda_stream)
         merged, mtot, mst = ms.candidates()
         views = [gpu_view(ms.scale(i), ms.cfgs[i]) for i in range(len(FACTORS))]
@@ -89,7 +93,8 @@ def test_multiscale_matches_oracle(store, nt):
     torch.cuda.synchronize()
     orc = []
     for f, c, g in zip(FACTORS, cfgs, views):
-        xb = cube if f == 1 else osr.bin_time(cube, f)
+        vals = input_values(cube, in_dtype)
+        xb = vals if f == 1 else osr.bin_time(vals, f)
         o = oracle_scale(xb, c)
         compare(g, o, c, tol=TOL if store == "f32" else 2e-4)
         orc.append(o)
