@@ -230,6 +230,22 @@ def snr_toa_margin_maps(z_tsp, delays, widths):
     return smax, toa, margin
 
 
+def trial_margin(smax):
+    """Per pixel, the gap between the best and the second-best snr_max over all
+    (DM, width) trials: inf where one trial alone has a window (or there is one
+    trial in all), nan where no trial has one. Decides where the best trial is
+    unambiguous."""
+    nd, nw, npix = smax.shape
+    if nd * nw == 1:
+        return np.full(npix, np.inf)
+    flat = np.where(np.isfinite(smax), smax, -np.inf).reshape(nd * nw, npix)
+    top2 = np.sort(flat, axis=0)[-2:]
+    out = np.full(npix, np.nan)
+    ok = np.isfinite(top2[1])
+    out[ok] = top2[1][ok] - top2[0][ok]          # second best -inf: inf
+    return out
+
+
 def bin_time(cube_tsp, factor):
     """Time binning for the longer search timescales (section 2.2: the images
     are also searched binned by 5 and by 75 samples).

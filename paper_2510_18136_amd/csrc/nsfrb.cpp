@@ -952,7 +952,8 @@ struct nsfrb_batch {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  std::vector<const void*> graph_ptrs;    // cube pointers baked into the graph
+  std::vector<const void*> desc_ptrs;     // cube pointers the device descriptors were written for
+  std::vector<const void*> graph_ptrs;    // cube pointers baked into the captured graph (if any)
   bool use_graph = true, last_graph = false, ran = false;
   hipEvent_t done = nullptr;
 };
@@ -1136,22 +1137,23 @@ extern "C" nsfrb_status nsfrb_batch_run(nsfrb_batch* b, const void* const* d_cub
   HIP_TRY(hipSetDevice(b->device));
   std::vector<const void*> ptrs(d_cubes, d_cubes + b->cubes.size());
   // descriptors carry the normalised-cube pointers; refresh them when the inputs change
-  const bool changed = ptrs != b->graph_ptrs;
-  if (changed || !b->ran) {
+  if (ptrs != b->desc_ptrs || !b->ran) {
     if (b->ran) HIP_TRY(hipEventSynchronize(b->done));
     for (size_t i = 0; i < b->cubes.size(); ++i) {
       nsfrb_search* h = b->cubes[i];
       b->descs[b->desc_of_cube[i]].z = h->cfg.layout == NSFRB_LAYOUT_TSP ? h->d_z : d_cubes[i];
     }
     HIP_TRY(hipMemcpy(b->d_descs, b->descs.data(), b->descs.size() * sizeof(CubeDescHost), hipMemcpyHostToDevice));
+    b->desc_ptrs = ptrs;
   }
   if (!b->use_graph) {
     nsfrb_status s = batch_enqueue(b, d_cubes, st);
     if (s != NSFRB_OK) return s;
     b->last_graph = false;
-    b->graph_ptrs = ptrs;
   } else {
-    if (changed || !b->exec) {
+    // the graph bakes in the raw cube pointers of its statistics launches:
+    // re-capture whenever they differ from this run's, whichever path ran last
+    if (ptrs != b->graph_ptrs || !b->exec) {
       if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
       if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
       HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));

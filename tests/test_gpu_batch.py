@@ -215,3 +215,43 @@ def test_full_size_batch_graph_equals_separate_and_oracle():
     assert np.abs(snr[fin] - o["snr_max"][fin]).max() <= 2e-4
     clear = fin & (o["margin"] > 2e-4)
     np.testing.assert_array_equal(toa[clear], o["toa"][clear])
+
+
+def test_batch_graph_after_plain_run_with_other_cubes():
+    """graph run on cubes A, plain run on cubes B, graph run on B: the last run
+    must search B (re-captured), not replay the graph captured for A."""
+    rng = np.random.default_rng(21)
+    cfgs = uneven_cfgs(rng, 4, "tsp", "f32")
+    stream = torch.cuda.current_stream()
+
+    def cubes(seed, pix_shift):
+        out = []
+        for i, c in enumerate(cfgs):
+            cube = synth.noise_cube(c.n_time, c.n_sub, c.n_pix, seed=seed + i)
+            off = delay_table(c.freqs, c.freqs.max(), 134.2, [428.0])[0]
+            synth.inject_boxcar(cube, (3 + pix_shift) % c.n_pix, 30, off, 8, 4.0)
+            out.append(to_device(cube, "f32"))
+        return out
+
+    a, bb = cubes(300, 0), cubes(400, 5)
+    pa, pb = [x.data_ptr() for x in a], [x.data_ptr() for x in bb]
+    with nsfrb.Batch(cfgs) as b:
+        print("[gpu] batch graph(A) -> plain(B) -> graph(B)", flush=True)
+        b.run_separate(pb, stream.cuda_stream)
+        ref_b = results(b, len(cfgs))
+        b.run_separate(pa, stream.cuda_stream)
+        ref_a = results(b, len(cfgs))
+        b.run(pa, stream.cuda_stream)
+        assert b.info()["graph"]
+        same(results(b, len(cfgs)), ref_a)
+        b.use_graph(False)
+        b.run(pb, stream.cuda_stream)
+        same(results(b, len(cfgs)), ref_b)
+        b.use_graph(True)
+        b.run(pb, stream.cuda_stream)
+        assert b.info()["graph"]
+        same(results(b, len(cfgs)), ref_b)
+        b.use_graph(False)
+        b.run(pa, stream.cuda_stream)
+        same(results(b, len(cfgs)), ref_a)
+    assert any(not np.array_equal(x[0], y[0]) for x, y in zip(ref_a, ref_b))

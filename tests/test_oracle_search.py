@@ -217,3 +217,54 @@ def test_binned_boxcar_snr_closed_form():
     assert coarse == pytest.approx(A * math.sqrt(ns * f * w), rel=1e-6)
     assert rs[1]["toa"][0, 2, 0] == 150 // f
     assert rs[1]["delays"].shape == (1, ns) and not rs[1]["delays"].any()
+
+
+def test_time_margin_on_hand_built_series():
+    """The S/N margin over time (best minus second best window of one trial),
+    which decides where TOAs are compared, on series worked out by hand:
+    one sub-band, DM 0, so S/N = window sum / sqrt(w)."""
+    z = np.array([1.0, 7.0, 3.0, 5.0, 5.0, -2.0])[:, None, None]
+    delays = np.zeros((1, 1), np.int32)
+    smax, toa, margin = osr.snr_toa_margin_maps(z, delays, [1, 2, 5, 6, 7])
+    # width 1: best 7 at t=1, next 5 -> margin 2
+    assert smax[0, 0, 0] == 7.0 and toa[0, 0, 0] == 1 and margin[0, 0, 0] == 2.0
+    # width 2: sums 8, 10, 8, 10, 3 -> exact tie at 10: margin 0, first maximum t=1
+    assert toa[0, 1, 0] == 1 and margin[0, 1, 0] == 0.0
+    assert smax[0, 1, 0] == pytest.approx(10 / math.sqrt(2), abs=0)
+    # width 5: sums 21 (t=0), 18 (t=1) -> margin 3/sqrt(5)
+    assert toa[0, 2, 0] == 0 and margin[0, 2, 0] == pytest.approx(3 / math.sqrt(5), rel=1e-15)
+    # width 6: one window -> inf; width 7: no window -> nan, -inf, -1
+    assert margin[0, 3, 0] == np.inf and smax[0, 3, 0] == pytest.approx(19 / math.sqrt(6))
+    assert np.isnan(margin[0, 4, 0]) and smax[0, 4, 0] == -np.inf and toa[0, 4, 0] == -1
+
+
+def test_time_margin_with_delays_and_pixels():
+    """Two sub-bands, delays (2, 0): D[t] = z0[t+2] + z1[t]; two pixels whose best
+    windows are a clear peak and an exact tie."""
+    z = np.zeros((8, 2, 2))
+    z[:, 0, 0] = [0, 0, 0, 4, 0, 0, 0, 0]      # D: z0 shifted by 2 -> peak at t=1
+    z[:, 1, 0] = [0, 3, 0, 0, 0, 1, 0, 0]      # D[1] = 4 + 3 = 7, D[5] = 1
+    z[:, 0, 1] = [0, 0, 2, 0, 0, 2, 0, 0]      # D[0] = 2, D[3] = 2 (tie) for pixel 1
+    delays = np.array([[2, 0]], np.int32)
+    smax, toa, margin = osr.snr_toa_margin_maps(z, delays, [1])
+    r2 = math.sqrt(2)
+    assert smax[0, 0, 0] == pytest.approx(7 / r2) and toa[0, 0, 0] == 1
+    assert margin[0, 0, 0] == pytest.approx(6 / r2)
+    assert toa[0, 0, 1] == 0 and margin[0, 0, 1] == 0.0
+
+
+def test_trial_margin_on_hand_built_maps():
+    """Margin between the best and second-best (DM, width) trial of a pixel."""
+    inf = np.inf
+    smax = np.array([[[5.0, 1.0, -inf, -inf, 2.0]],
+                     [[3.0, 1.0, -inf, 4.0, 2.0]]])        # [d=2][w=1][p=5]
+    m = osr.trial_margin(smax)
+    assert m[0] == 2.0                 # 5 vs 3
+    assert m[1] == 0.0                 # exact tie 1 vs 1
+    assert np.isnan(m[2])              # no trial has a window
+    assert m[3] == inf                 # a single trial has a window: unambiguous
+    assert m[4] == 0.0
+    assert (osr.trial_margin(smax[:1]) == inf).all()   # one trial in total
+    # agrees with the per-pixel best: the best trial is unique wherever m > 0
+    best, bd, bw, _ = osr.best_per_pixel(smax, np.zeros(smax.shape, np.int32))
+    assert bd[0] == 0 and best[0] == 5.0
