@@ -360,6 +360,22 @@ typedef struct {
 nsfrb_status nsfrb_inject_boxcars(void* const* d_cubes, int32_t n_cubes, int32_t dtype, int32_t layout, int32_t n_pix,
                                   int32_t n_sub, int32_t n_time, const nsfrb_boxcar* host_boxcars,
                                   const int32_t* host_offsets, int32_t n, void* stream);
+/* nsfrb_inject_boxcars for callers that cannot allocate device memory (a
+ * serving loop injecting test pulses into live data, code that forbids
+ * hipMalloc): same arguments, same kernel, same result, but the host tables
+ * are staged in a static device array of NSFRB_INJECT_STATIC_BYTES per GPU
+ * (held until the process ends) instead of a per-call allocation; the call
+ * makes no hipMalloc/hipFree. Limits: n <= 4096, and
+ * align256(8 * n_cubes) + align256(20 * n) + 4 * n * n_sub <= 1 MiB
+ * (align256 rounds up to a multiple of 256); beyond them INVALID_ARG, nothing
+ * copied or launched. Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (other host threads, other streams) race and must be
+ * serialised by the caller. Synchronous on `stream`. */
+#define NSFRB_INJECT_STATIC_BYTES (1u << 20)
+nsfrb_status nsfrb_inject_boxcars_static(void* const* d_cubes, int32_t n_cubes, int32_t dtype, int32_t layout,
+                                         int32_t n_pix, int32_t n_sub, int32_t n_time,
+                                         const nsfrb_boxcar* host_boxcars, const int32_t* host_offsets, int32_t n,
+                                         void* stream);
 /* Interference over all pixels (synthetic RFI): kind 0 adds `amp` to sample
  * t0 of every sub-band (a zero-DM spike); kind 1 adds `amp` to samples
  * t0 .. t0+len-1 of sub-band `sub_band` (a stripe). Samples outside are skipped. */

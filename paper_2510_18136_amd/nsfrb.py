@@ -33,7 +33,7 @@ EXPORTS = [
     "nsfrb_batch_create", "nsfrb_batch_destroy", "nsfrb_batch_run", "nsfrb_batch_run_separate",
     "nsfrb_batch_use_graph", "nsfrb_batch_candidates_get", "nsfrb_batch_maps_get", "nsfrb_batch_best_get",
     "nsfrb_batch_zcube_device", "nsfrb_batch_info_get",
-    "nsfrb_generate_noise", "nsfrb_inject_boxcar", "nsfrb_inject_boxcars", "nsfrb_philox_fill", "nsfrb_inject_rfi",
+    "nsfrb_generate_noise", "nsfrb_inject_boxcar", "nsfrb_inject_boxcars", "nsfrb_inject_boxcars_static", "nsfrb_philox_fill", "nsfrb_inject_rfi",
     "nsfrb_classifier_param_count", "nsfrb_classifier_create", "nsfrb_classifier_destroy",
     "nsfrb_classifier_params_get", "nsfrb_classifier_params_set", "nsfrb_classifier_set_lr",
     "nsfrb_classifier_grads_get",
@@ -147,6 +147,8 @@ def lib():
                                     ctypes.c_int),
             "nsfrb_inject_boxcars": ([ctypes.POINTER(vp), i32, i32, i32, i32, i32, i32, ctypes.POINTER(Boxcar),
                                       pi32, i32, vp], ctypes.c_int),
+            "nsfrb_inject_boxcars_static": ([ctypes.POINTER(vp), i32, i32, i32, i32, i32, i32,
+                                             ctypes.POINTER(Boxcar), pi32, i32, vp], ctypes.c_int),
             "nsfrb_philox_fill": ([vp, ctypes.c_int64, ctypes.c_uint64, vp], ctypes.c_int),
             "nsfrb_inject_rfi": ([vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, ctypes.c_float, vp], ctypes.c_int),
             "nsfrb_classifier_param_count": ([], ctypes.c_int32),
@@ -608,15 +610,19 @@ def inject_boxcar(d_ptr, dtype, layout, n_pix, n_sub, n_time, pixel, t0, width, 
                                     ctypes.c_void_p(int(stream))))
 
 
-def inject_boxcars(d_ptrs, dtype, layout, n_pix, n_sub, n_time, boxcars, offsets, stream=0):
-    """boxcars: (cube, pixel, t0, width, amp) tuples; offsets: [n][n_sub] sample shifts."""
+def inject_boxcars(d_ptrs, dtype, layout, n_pix, n_sub, n_time, boxcars, offsets, stream=0, static=False):
+    """boxcars: (cube, pixel, t0, width, amp) tuples; offsets: [n][n_sub] sample shifts.
+
+    static=True calls nsfrb_inject_boxcars_static (tables staged in the
+    library's static device array; no device allocation)."""
     off = np.ascontiguousarray(offsets, dtype=np.int32)
     n = len(boxcars)
     assert off.shape == (n, n_sub)
     ptrs = (ctypes.c_void_p * len(d_ptrs))(*[ctypes.c_void_p(int(p)) for p in d_ptrs])
     recs = (Boxcar * n)(*[Boxcar(int(k), int(p), int(t), int(w), float(a)) for (k, p, t, w, a) in boxcars])
-    check(lib().nsfrb_inject_boxcars(ptrs, len(d_ptrs), DTYPES[dtype], LAYOUTS[layout], n_pix, n_sub, n_time, recs,
-                                     _ptr(off, ctypes.c_int32), n, ctypes.c_void_p(int(stream))))
+    fn = lib().nsfrb_inject_boxcars_static if static else lib().nsfrb_inject_boxcars
+    check(fn(ptrs, len(d_ptrs), DTYPES[dtype], LAYOUTS[layout], n_pix, n_sub, n_time, recs,
+             _ptr(off, ctypes.c_int32), n, ctypes.c_void_p(int(stream))))
 
 
 def philox_fill(d_ptr, n_blocks, seed, stream=0):
