@@ -150,11 +150,46 @@ def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, 
     print(json.dumps(rec, indent=1))
 
 
-def cpu_baseline(cube, meta, target_s=12.0):
-    """Time the FP64 oracle on a bounded pixel sample of the same workload."""
+def host_info():
+    """The host the oracle runs on: logical CPUs, CPUs this process may use, CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpus_usable": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+_ORACLE_JOB = {}     # inherited by forked workers: the cube, the meta data, the pixel sample
+
+
+def _oracle_pixels(bounds):
+    """Oracle on pixels [lo, hi) of the sample (a forked worker; one NumPy thread)."""
     from oracle import search as osr
+    lo, hi = bounds
+    cube, meta, pix = _ORACLE_JOB["cube"], _ORACLE_JOB["meta"], _ORACLE_JOB["pix"][lo:hi]
+    sub = np.ascontiguousarray(cube[:, :, pix])
+    osr.search(sub, meta["freqs"], meta["f_ref"], meta["dt_ms"], meta["dms"], meta["widths"], len(pix),
+               theta=meta["theta"])
+    return hi - lo
+
+
+def cpu_baseline(cube, meta, target_s=12.0, max_workers=16):
+    """Time the FP64 oracle on bounded pixel samples of the same workload: one
+    process (NumPy is single-threaded here), then the pixel sample split over
+    the usable CPUs (at most max_workers processes, forked so the cube is
+    shared), and the oracle on the tiny workload."""
+    import multiprocessing as mp
+
+    from oracle import search as osr
+    from paper_2510_18136_amd import synth
     rng = np.random.default_rng(123)
     n_pix = cube.shape[2]
+    trials_per_pixel = len(meta["dms"]) * len(meta["widths"])
 
     def once(n):
         pix = np.sort(rng.choice(n_pix, size=n, replace=False))
@@ -165,12 +200,39 @@ def cpu_baseline(cube, meta, target_s=12.0):
         return time.perf_counter() - t0
 
     t_cal = once(32)                               # calibrate, then one run of ~target_s
-    n = int(min(4096, max(32, 32 * target_s / max(t_cal, 1e-3))))
-    elapsed = once(n)
-    trials = n * len(meta["dms"]) * len(meta["widths"])
-    return {"value": trials / elapsed, "unit": "trials/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} random pixels of the same cube (all 16 sub-bands x 2048 samples, all 32 DMs x "
-                      f"12 widths), {elapsed:.2f} s of NumPy FP64 on one thread"}
+    n1 = int(min(4096, max(32, 32 * target_s / max(t_cal, 1e-3))))
+    el1 = once(n1)
+    single = {"value": n1 * trials_per_pixel / el1, "unit": "trials/s", "cores": 1, "kind": "oracle",
+              "sample": f"{n1} random pixels of the same cube (all 16 sub-bands x 2048 samples, all 32 DMs x "
+                        f"12 widths), {el1:.2f} s of NumPy FP64 in one process"}
+    workers = max(1, min(max_workers, len(os.sched_getaffinity(0))))
+    per = max(8, int(n1 * 1.0))                   # about the single leg's time per worker
+    n_all = min(n_pix, per * workers)
+    pix = np.sort(rng.choice(n_pix, size=n_all, replace=False))
+    _ORACLE_JOB.update(cube=cube, meta=meta, pix=pix)
+    bounds = [(k * n_all // workers, (k + 1) * n_all // workers) for k in range(workers)]
+    for name in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[name] = "1"
+    with mp.get_context("fork").Pool(workers) as pool:
+        t0 = time.perf_counter()
+        done = sum(pool.map(_oracle_pixels, bounds))
+        el_all = time.perf_counter() - t0
+    _ORACLE_JOB.clear()
+    # the tiny workload (32x32 px, 4 sub-bands, 64 samples, 8 DMs, widths 1-16), one process
+    c1, m1 = synth.config1()
+    t0, reps = time.perf_counter(), 0
+    while reps < 3 or time.perf_counter() - t0 < 2.0:
+        osr.search(c1, m1["freqs"], m1["f_ref"], m1["dt_ms"], m1["dms"], m1["widths"], m1["nx"], theta=m1["theta"])
+        reps += 1
+    c1_ms = (time.perf_counter() - t0) * 1e3 / reps
+    out = {"value": done * trials_per_pixel / el_all, "unit": "trials/s", "cores": workers, "kind": "oracle",
+           "sample": f"{done} random pixels of the same cube (all 16 sub-bands x 2048 samples, all 32 DMs x 12 "
+                     f"widths) split over {workers} forked processes, {el_all:.2f} s wall",
+           "single_process": single,
+           "tiny_workload": {"ms_per_run": c1_ms, "runs": reps, "trials_per_s": 32 * 32 * 8 * 5 / (c1_ms * 1e-3),
+                             "cores": 1}}
+    out.update(host_info())
+    return out
 
 
 def bench_batch(nsfrb, hip, reps=3):
@@ -413,6 +475,88 @@ def bench_tiny(nsfrb, hip, synth, reps=200):
             "us_per_run": us, "runs": reps, "trials_per_s": 32 * 32 * 8 * 5 / (us * 1e-6)}
 
 
+def torch_leg(steps, warmup):
+    """The survey-shape FP32 search in a process that imports PyTorch first (the
+    integration path of a torch caller: torch allocates the cube and owns the
+    stream; the library then shares the HIP runtime the torch wheel loads).
+    Prints one JSON line; run as a child process by main()."""
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible to torch"}), flush=True)
+        return
+    from paper_2510_18136_amd import nsfrb, synth
+    n_pix, n_t, n_sub = 256 * 256, 2048, 16
+    x = torch.empty(n_t * n_sub * n_pix, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    nsfrb.generate_noise(x.data_ptr(), "f32", "tsp", n_pix, n_sub, n_t, 2, stream=stream)
+    cfg = nsfrb.SearchConfig(256, 256, n_t, synth.C2_FREQS, np.linspace(0.0, 4000.0, 32),
+                             synth.widths_pow2(1024, (1200,)), snr_threshold=6.0)
+    s = nsfrb.Search(cfg)
+    for _ in range(warmup):
+        s.run(x.data_ptr(), stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        s.run(x.data_ptr(), stream)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    s.profiling(True)
+    st = np.zeros(3)
+    for _ in range(3):
+        s.run(x.data_ptr(), stream)
+        st += s.stage_times_ms()
+    s.profiling(False)
+    plan = s.plan_info()
+    s.close()
+    print(json.dumps({"ms_per_step": ms, "stage_ms": dict(zip(("stats_norm", "search", "candidates"),
+                                                              (st / 3).tolist())),
+                      "search_plan": plan, "torch": torch.__version__}), flush=True)
+
+
+def classifier_gain_leg():
+    """The learned stage against the plain S/N >= 6 threshold: train on 200k
+    fresh search-made cutouts, choose the operating point on 10k validation
+    cutouts, evaluate on 10k held-out ones (seeded; the training driver uses
+    torch for its buffers). Prints one JSON line; run as a child process."""
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible to torch"}), flush=True)
+        return
+    from paper_2510_18136_amd import nsfrb, train_classifier as tc
+    t0 = time.time()
+    with nsfrb.Classifier(max_batch=64, n_time=tc.CUT_T, ny=32, lr=1e-3, seed=1) as clf:
+        tr = tc.train(clf, 200_000, seed=1001, lr=1e-3, log=lambda m: None)
+        val = tc.score(clf, 10_000, seed=1002)
+        held = tc.score(clf, 10_000, seed=1003)
+    res = tc.evaluate(val, held)
+    print(json.dumps({"train_cutouts": tr["cutouts"], "train_steps": tr["steps"], "train_seconds": tr["seconds"],
+                      "wall_seconds": time.time() - t0, "heldout": res}), flush=True)
+
+
+def run_child(flag, steps=None, warmup=None, timeout=600):
+    """Run bench.py `flag` in a child process (torch is imported only there) and
+    return its JSON line."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), flag]
+    if steps is not None:
+        cmd += ["--steps", str(steps), "--warmup", str(warmup)]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=timeout)
+    for line in reversed(r.stdout.strip().splitlines()):
+        if line.startswith("{"):
+            return json.loads(line)
+    return {"error": f"{flag} exited with {r.returncode}: {r.stderr[-400:]}"}
+
+
+def run_torch_leg(steps, warmup):
+    """Time the survey-shape search in a child process that imports torch first."""
+    out = run_child("--torch-leg", steps, warmup)
+    out["workload"] = ("the survey-shape FP32 search (device noise, same shape and grid) in a process "
+                       "that imports PyTorch first; torch owns the cube and the stream")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -426,12 +570,22 @@ def main():
     ap.add_argument("--no-multiscale", action="store_true")
     ap.add_argument("--no-psf", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-torch-leg", action="store_true")
+    ap.add_argument("--torch-leg", action="store_true", help="(internal) run only the torch-process leg")
+    ap.add_argument("--no-classifier-gain", action="store_true")
+    ap.add_argument("--classifier-gain", action="store_true", help="(internal) run only the classifier-gain leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (counter calibration)")
     ap.add_argument("--traffic-from", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV",
                                                         "COPY_BYTES"),
                     help="write profiles/hbm_traffic.json from rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
+    if args.torch_leg:
+        torch_leg(args.steps, args.warmup)
+        return
+    if args.classifier_gain:
+        classifier_gain_leg()
+        return
     if args.traffic_from:
         traffic_from_counters(*args.traffic_from[:4], int(args.traffic_from[4]))
         return
@@ -458,6 +612,7 @@ def main():
     xbuf = hip.Buffer(cube.nbytes).upload(cube)
     hip.synchronize()
     x_ptr = xbuf.ptr
+    flush = hip.Buffer(512 << 20)
 
     def make(store):
         cfg = nsfrb.SearchConfig(meta["nx"], meta["ny"], cube.shape[0], meta["freqs"], meta["dms"],
@@ -477,6 +632,17 @@ def main():
         hip.synchronize()
         wall = (time.perf_counter() - w0) * 1e3 / steps
         tm.close()
+        # the same step timed alone, 512 MB written between steps so that no part
+        # of the cube is served from the 256 MB Infinity Cache; median of the reps
+        flushed = []
+        tf = hip.Timer()
+        for _ in range(max(5, min(steps, 20))):
+            flush.zero()
+            tf.start()
+            search.run(x_ptr, 0)
+            flushed.append(tf.stop())
+        tf.close()
+        med_flushed = float(np.median(flushed))
         # per-stage device times (HIP events on the run's stream), averaged over a few runs
         search.profiling(True)
         st = np.zeros(3)
@@ -485,11 +651,11 @@ def main():
             search.run(x_ptr, 0)
             st += search.stage_times_ms()
         search.profiling(False)
-        return max(wall, ev), st / nrep
+        return max(wall, ev), st / nrep, med_flushed
 
     cfg, s32 = make("f32")
     print("[bench] fp32 plan ready", file=sys.stderr, flush=True)
-    ms, stages = timed(s32, args.steps, args.warmup)
+    ms, stages, ms_flushed = timed(s32, args.steps, args.warmup)
     cands, ntot, _ = s32.candidates()
     print(f"[bench] fp32 {ms:.3f} ms/step, stages {stages.round(3).tolist()} ms, {ntot} candidates",
           file=sys.stderr, flush=True)
@@ -518,15 +684,17 @@ def main():
                                   "100 pulses, 20 zero-DM spikes, 2 stripes (seed 2)",
                       "pixels": n_pix, "sub_bands": 16, "samples": 2048, "dm_trials": n_dm, "widths": n_w},
            "stage_ms": {"stats_norm": stages[0], "search": stages[1], "candidates": stages[2]},
+           "ms_per_step_median_cache_flushed": ms_flushed,
            "roofline": roof, "hbm": hbm, "candidates_found": ntot, "search_plan": plan32,
            "trial_samples_per_s": valid_windows(n_pix, cube.shape[0], delays, meta["widths"]) / (ms * 1e-3)}
     s32.close()
     if not args.no_fp16:
         cfg16, s16 = make("f16")
-        ms16, st16 = timed(s16, args.steps, args.warmup)
+        ms16, st16, ms16_flushed = timed(s16, args.steps, args.warmup)
         plan16 = s16.plan_info()
         s16.close()
         out["fp16_store"] = {"ms_per_step": ms16, "value": trials / (ms16 * 1e-3),
+                             "ms_per_step_median_cache_flushed": ms16_flushed,
                              "stage_ms": {"stats_norm": st16[0], "search": st16[1], "candidates": st16[2]},
                              "speedup_vs_fp32": ms / ms16, "search_speedup_vs_fp32": stages[1] / st16[1],
                              "search_plan": plan16}
@@ -541,12 +709,13 @@ def main():
             c = nsfrb.SearchConfig(meta["nx"], meta["ny"], cube.shape[0], meta["freqs"], pg_dms, pg_w,
                                    store_dtype=store, snr_threshold=meta["theta"])
             sp = nsfrb.Search(c)
-            m, st = timed(sp, args.steps, args.warmup)
+            m, st, m_flushed = timed(sp, args.steps, args.warmup)
             info = sp.plan_info()
             sp.close()
             b2, o2 = algorithmic_counts(n_pix, 16, cube.shape[0], c.delays(), pg_w, sb)
             ts = st[1] * 1e-3
             pg[store] = {"ms_per_step": m, "trials_per_s": n_pix * 16 * 5 / (m * 1e-3),
+                         "ms_per_step_median_cache_flushed": m_flushed,
                          "stage_ms": {"stats_norm": st[0], "search": st[1], "candidates": st[2]},
                          "search_hbm_GBs": b2 / ts / 1e9, "search_hbm_frac": b2 / ts / 1e9 / PEAK_HBM_GBS,
                          "search_alu_frac": o2 / ts / 1e12 / PEAK_ALU_TOPS,
@@ -566,6 +735,7 @@ def main():
               f"search), S/N ratio {mt['snr_recovery']['median_snr_ratio_multiscale_over_exact']:.3f}",
               file=sys.stderr, flush=True)
     xbuf.close()
+    flush.close()
     if not args.no_psf:
         out["psf_reduction"] = bench_psf(nsfrb, hip, synth)
         pr = out["psf_reduction"]
@@ -583,6 +753,27 @@ def main():
         out["classifier"] = bench_classifier(nsfrb, hip)
         print(f"[bench] classifier train {out['classifier']['train_ms_per_step']:.2f} ms/step "
               f"({out['classifier']['train_TFLOPs']:.1f} TFLOP/s)", file=sys.stderr, flush=True)
+    if not args.no_torch_leg:
+        print("[bench] survey-shape search in a torch process (child)", file=sys.stderr, flush=True)
+        out["torch_process"] = run_torch_leg(min(args.steps, 10), args.warmup)
+        tl = out["torch_process"]
+        if "ms_per_step" in tl:
+            tl["slowdown_vs_value"] = tl["ms_per_step"] / ms
+            print(f"[bench] torch process: {tl['ms_per_step']:.2f} ms/step (search {tl['stage_ms']['search']:.2f} ms)",
+                  file=sys.stderr, flush=True)
+    if not args.no_classifier_gain:
+        print("[bench] classifier gain: 200k training cutouts, 10k validation, 10k held-out (child)",
+              file=sys.stderr, flush=True)
+        cg = run_child("--classifier-gain", timeout=900)
+        if "heldout" in cg:
+            ev = cg["heldout"]
+            cg["summary"] = {"threshold_recall": ev["snr_threshold"]["recall"],
+                             "threshold_false": ev["snr_threshold"]["false_candidates"],
+                             "classifier_recall": ev["classifier_matched"]["recall"],
+                             "classifier_false": ev["classifier_matched"]["false_candidates"],
+                             "false_candidate_reduction": ev["false_candidate_reduction"]}
+            print(f"[bench] classifier gain: {cg['summary']}", file=sys.stderr, flush=True)
+        out["classifier_gain"] = cg
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a pixel sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cube, meta)

@@ -186,10 +186,13 @@ nsfrb_status nsfrb_maps_device(nsfrb_search* h, float** snr_max, int32_t** toa);
 nsfrb_status nsfrb_profiling_enable(nsfrb_search* h, int32_t on);
 nsfrb_status nsfrb_stage_times_get(nsfrb_search* h, float* ms3);
 
-/* Plan of the search kernel: info[0] samples per lane, info[1] pixels per
- * workgroup, info[2] LDS row length, info[3] LDS bytes per workgroup, info[4]
- * threads per workgroup (pixels and threads per workgroup chosen by the
- * autotuner); host_out holds 5 values. */
+/* Plan of the search kernel the autotuner chose: info[0] samples per lane,
+ * info[1] pixels per workgroup, info[2] LDS row length, info[3] LDS bytes per
+ * workgroup, info[4] threads per workgroup, info[5] 1 if the persistent kernel
+ * (one pixel per workgroup at a time, next pixel's rows loaded during the
+ * search of the current one) was chosen, else 0; for it, info[6] LDS pixel
+ * buffers and info[7] workgroups (0 otherwise); info[8] is 0. `info` holds 9
+ * values. */
 nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* info);
 
 /* ---------------------------------------------------------- multi-timescale
@@ -291,9 +294,11 @@ nsfrb_status nsfrb_stream_search(nsfrb_stream* s, nsfrb_search** out);
  * linear interpolation between order statistics, as NumPy's default) into a
  * binary mask (pixels >= the threshold). The mask is centred on each candidate
  * in turn: the other candidates at offsets inside it are that candidate's
- * possible sidelobes, and its score is the weighted mean S/N over itself
- * (weight 1) and them (weight = PSF at the offset / PSF at the centre). Writes
- * the index of the highest score (ties: the earlier candidate) and that score.
+ * possible sidelobes, and its score is the S/N of the weighted mean of the
+ * S/N values of itself (weight 1) and them (weight w = PSF at the offset / PSF
+ * at the centre): sum(w S) / sqrt(sum(w^2)), each S/N having unit noise.
+ * Writes the index of the highest score (ties: the earlier candidate) and that
+ * score.
  * INVALID_ARG for NULL pointers, n < 1, even sides, a non-finite PSF value, a
  * centre <= 0 or a percentile outside 0..100. */
 nsfrb_status nsfrb_psf_reduce(const nsfrb_candidate* cands, int32_t n, const float* psf, int32_t psf_nx,
@@ -431,6 +436,23 @@ nsfrb_status nsfrb_classifier_params_set(nsfrb_classifier* c, const float* host_
 nsfrb_status nsfrb_classifier_set_lr(nsfrb_classifier* c, float lr);
 /* Gradient of the mean loss from the last train step (same layout as the parameters). */
 nsfrb_status nsfrb_classifier_grads_get(nsfrb_classifier* c, float* host_out);
+/* Checkpoints of training (section 2.3 trains with Adam; a run that stops
+ * resumes with the same result): a host byte image of
+ * nsfrb_classifier_state_bytes() bytes holding a 56-byte header (magic
+ * "NSFRBCK1", version 1, parameter count, Adam step count, the caller's
+ * `user_counter` word, lr, beta1, beta2, eps, n_time, ny) followed by the FP32
+ * parameters and Adam's first and second moments (param_count values each).
+ * Train steps after nsfrb_classifier_load continue exactly as they would have
+ * after the save (same weights, moments, step count and bias corrections).
+ * save: waits for the device; capacity < state_bytes -> TRUNCATED (n_written
+ * still set). load: INVALID_ARG if the size, magic, version, parameter count or
+ * cutout shape (n_time, ny) differ from this classifier's, or the optimiser
+ * settings are not finite; nothing is changed then. *user_counter (may be
+ * NULL) receives the saved word. */
+int64_t nsfrb_classifier_state_bytes(void);
+nsfrb_status nsfrb_classifier_save(nsfrb_classifier* c, uint64_t user_counter, void* host_out, int64_t capacity,
+                                   int64_t* n_written);
+nsfrb_status nsfrb_classifier_load(nsfrb_classifier* c, const void* host_in, int64_t n_bytes, uint64_t* user_counter);
 /* One step on n cutouts (device BF16 [n][n_time][ny][32][16]) with device FP32
  * labels (1 = RFI/noise, 0 = astrophysical): forward, BCE loss, backward and,
  * if `update`, one Adam step. *host_loss (may be NULL) receives the mean loss
@@ -440,6 +462,16 @@ nsfrb_status nsfrb_classifier_train_step(nsfrb_classifier* c, const void* d_cuto
 /* p_rfi = sigmoid(logit) for n cutouts into device d_prob[n]. */
 nsfrb_status nsfrb_classifier_infer(nsfrb_classifier* c, const void* d_cutouts, int32_t n, float* d_prob,
                                     void* stream);
+/* Test/introspection: after a train step or inference on n' >= n cutouts, the
+ * BF16 output a_layer (layer 1..4) of that forward pass for its first n
+ * cutouts, host_out uint16 [n][n_time][ny][32][32] (BF16 bits); after a train
+ * step, the BF16 gradient of the loss with respect to conv layer `layer`'s
+ * pre-activation (ReLU derivative applied), same layout; and the FP32 logits
+ * z (p_rfi = sigmoid(z)), host_out[n]. Wait for the device. INVALID_ARG for
+ * NULL pointers, layer outside 1..4 or n outside 1..max_batch. */
+nsfrb_status nsfrb_classifier_activations_get(nsfrb_classifier* c, int32_t layer, int32_t n, void* host_out);
+nsfrb_status nsfrb_classifier_grad_pre_get(nsfrb_classifier* c, int32_t layer, int32_t n, void* host_out);
+nsfrb_status nsfrb_classifier_logits_get(nsfrb_classifier* c, int32_t n, float* host_out);
 /* Cut n_cut dedispersion-aligned cutouts (section 2.3: the classifier sees
  * the image cube centred on the candidate's TOA) out of normalised cubes in
  * the search layout [ny*nx][n_sub][n_time] (store dtype; n_sub must be 16).

@@ -116,18 +116,7 @@ def forward(theta, x, bf16_points=False):
     for l in range(4):
         W, b = P[2 * l], P[2 * l + 1]
         acts.append(rnd(np.maximum(conv3(acts[-1], rnd(W), b), 0.0)))
-    a4 = acts[-1]
-    n, T, Y, X, C = a4.shape
-    flat = a4.reshape(n, T * Y * X, C)
-    arg = np.argmax(flat, axis=1)                      # first maximum along (t, y, x)
-    m = np.take_along_axis(flat, arg[:, None, :], axis=1)[:, 0, :]
-    q = a4[:, T // 2, Y // 2, X // 2, :]
-    h = np.concatenate([m, q], axis=1)
-    W1, c1, w2, c2 = P[8], P[9], P[10], P[11]
-    u = h @ W1.T + c1
-    r = np.maximum(u, 0.0)
-    z = r @ w2 + c2[0]
-    return dict(acts=acts, arg=arg, h=h, u=u, r=r, z=z)
+    return dict(acts=acts, **head_forward(theta, acts[-1]))
 
 
 def pool_backward(a4_shape, arg, dh):
@@ -146,26 +135,48 @@ def bce_logits(z, y):
     return float(np.mean(np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z)))))
 
 
-def loss_and_grad(theta, x, labels, bf16_points=False, input_grad=False):
-    """Mean BCE-with-logits loss and its gradient w.r.t. the flat parameters
-    (and, with input_grad, w.r.t. the input cutouts as a fourth value)."""
+def head_backward(theta, f, labels):
+    """From a forward record f (its h, u, r, z, arg and a_4): the mean BCE loss,
+    the head's parameter gradients (W1, c1, w2, c2) and d(loss)/d(a_4)."""
     P = unpack(theta)
-    rnd = bf16 if bf16_points else (lambda a: a)
-    f = forward(theta, x, bf16_points)
     y = np.asarray(labels, dtype=np.float64)
     n = y.size
     loss = bce_logits(f["z"], y)
     dz = (1.0 / (1.0 + np.exp(-f["z"])) - y) / n
-    W1, c1, w2, c2 = P[8], P[9], P[10], P[11]
+    W1, w2 = P[8], P[10]
     g_w2 = f["r"].T @ dz
     g_c2 = np.array([dz.sum()])
     du = np.outer(dz, w2) * (f["u"] > 0)
     g_W1 = du.T @ f["h"]
     g_c1 = du.sum(axis=0)
     dh = du @ W1
-    dpost = pool_backward(f["acts"][4].shape, f["arg"], dh)
+    return loss, (g_W1, g_c1, g_w2, g_c2), pool_backward(f["acts"][4].shape, f["arg"], dh)
+
+
+def head_forward(theta, a4):
+    """The head on conv-4 outputs a4: the forward record fields h, u, r, z, arg."""
+    P = unpack(theta)
+    n, T, Y, X, C = a4.shape
+    flat = a4.reshape(n, T * Y * X, C)
+    arg = np.argmax(flat, axis=1)                      # first maximum along (t, y, x)
+    m = np.take_along_axis(flat, arg[:, None, :], axis=1)[:, 0, :]
+    q = a4[:, T // 2, Y // 2, X // 2, :]
+    h = np.concatenate([m, q], axis=1)
+    u = h @ P[8].T + P[9]
+    r = np.maximum(u, 0.0)
+    z = r @ P[10] + P[11][0]
+    return dict(arg=arg, h=h, u=u, r=r, z=z)
+
+
+def loss_and_grad(theta, x, labels, bf16_points=False, input_grad=False):
+    """Mean BCE-with-logits loss and its gradient w.r.t. the flat parameters
+    (and, with input_grad, w.r.t. the input cutouts as a fourth value)."""
+    P = unpack(theta)
+    rnd = bf16 if bf16_points else (lambda a: a)
+    f = forward(theta, x, bf16_points)
+    loss, head_grads, dpost = head_backward(theta, f, labels)
     grads = [None] * 12
-    grads[8], grads[9], grads[10], grads[11] = g_W1, g_c1, g_w2, g_c2
+    grads[8], grads[9], grads[10], grads[11] = head_grads
     for l in (3, 2, 1, 0):
         dpre = rnd(dpost * (f["acts"][l + 1] > 0))
         dW, db, dx = conv3_backward(f["acts"][l], rnd(P[2 * l]), dpre, need_dx=l > 0 or input_grad)

@@ -60,7 +60,7 @@ struct nsfrb_classifier {
   uint16_t* d_wf[4] = {};      // BF16 forward weights in convolution-operand order
   uint16_t* d_wb[4] = {};      // BF16 backward-data weights (flipped taps, transposed channels; layers 2..4)
   uint16_t* d_act[4] = {};     // conv outputs a_1..a_4 [n][t][y][x][32]
-  uint16_t* d_dpre[2] = {};    // pre-activation gradients (ping-pong)
+  uint16_t* d_dpre[4] = {};    // pre-activation gradients of conv layers 1..4 (kept for inspection)
   float* d_part = nullptr;
   float* d_part_db = nullptr;
   float* d_h = nullptr;         // head input [n][64]: channel maxima, candidate-position features
@@ -223,6 +223,91 @@ extern "C" nsfrb_status nsfrb_classifier_params_set(nsfrb_classifier* c, const f
   return NSFRB_OK;
 }
 
+// ------------------------------------------------------------ checkpoints
+// A checkpoint is a host byte image: a fixed header, then the FP32 parameter
+// vector, then Adam's first and second moments (each nsfrb_classifier_param_count
+// values, little-endian as the host stores them).
+namespace {
+struct CkptHeader {
+  char magic[8];            // "NSFRBCK1"
+  uint32_t version;         // 1
+  uint32_t n_params;
+  int64_t step;             // Adam steps taken (bias corrections continue from it)
+  uint64_t user_counter;    // caller's word, e.g. the position of its data generator
+  float lr, beta1, beta2, eps;
+  int32_t n_time, ny;       // cutout shape the classifier was created for
+};
+static_assert(sizeof(CkptHeader) == 56, "checkpoint header layout");
+constexpr char kCkptMagic[8] = {'N', 'S', 'F', 'R', 'B', 'C', 'K', '1'};
+}  // namespace
+
+extern "C" int64_t nsfrb_classifier_state_bytes(void) {
+  return (int64_t)sizeof(CkptHeader) + 3 * (int64_t)sizeof(float) * kL.total;
+}
+
+extern "C" nsfrb_status nsfrb_classifier_save(nsfrb_classifier* c, uint64_t user_counter, void* host_out,
+                                              int64_t capacity, int64_t* n_written) {
+  host_clear_error();
+  if (!c || !host_out || !n_written) return host_fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  const int64_t need = nsfrb_classifier_state_bytes();
+  *n_written = need;
+  if (capacity < need) return host_fail(NSFRB_ERR_TRUNCATED, "capacity below nsfrb_classifier_state_bytes()");
+  NSFRB_HIP_TRY(hipSetDevice(c->device));
+  NSFRB_HIP_TRY(hipDeviceSynchronize());
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = 1;
+  h.n_params = (uint32_t)kL.total;
+  h.step = c->step;
+  h.user_counter = user_counter;
+  h.lr = c->cfg.lr;
+  h.beta1 = c->cfg.beta1;
+  h.beta2 = c->cfg.beta2;
+  h.eps = c->cfg.eps;
+  h.n_time = c->cfg.n_time;
+  h.ny = c->cfg.ny;
+  unsigned char* out = static_cast<unsigned char*>(host_out);
+  std::memcpy(out, &h, sizeof h);
+  float* body = reinterpret_cast<float*>(out + sizeof h);
+  const size_t nb = sizeof(float) * kL.total;
+  NSFRB_HIP_TRY(hipMemcpy(body, c->d_theta, nb, hipMemcpyDeviceToHost));
+  NSFRB_HIP_TRY(hipMemcpy(body + kL.total, c->d_m, nb, hipMemcpyDeviceToHost));
+  NSFRB_HIP_TRY(hipMemcpy(body + 2 * kL.total, c->d_v, nb, hipMemcpyDeviceToHost));
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_classifier_load(nsfrb_classifier* c, const void* host_in, int64_t n_bytes,
+                                              uint64_t* user_counter) {
+  host_clear_error();
+  if (!c || !host_in) return host_fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  if (n_bytes != nsfrb_classifier_state_bytes())
+    return host_fail(NSFRB_ERR_INVALID_ARG, "checkpoint size differs from nsfrb_classifier_state_bytes()");
+  CkptHeader h;
+  std::memcpy(&h, host_in, sizeof h);
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+    return host_fail(NSFRB_ERR_INVALID_ARG, "not a classifier checkpoint (magic or version)");
+  if (h.n_params != (uint32_t)kL.total || h.n_time != c->cfg.n_time || h.ny != c->cfg.ny)
+    return host_fail(NSFRB_ERR_INVALID_ARG, "checkpoint of another network or cutout shape");
+  if (h.step < 0 || !std::isfinite(h.lr) || !(h.lr >= 0.f) || !std::isfinite(h.beta1) || !std::isfinite(h.beta2) ||
+      !std::isfinite(h.eps))
+    return host_fail(NSFRB_ERR_INVALID_ARG, "checkpoint header holds invalid optimiser settings");
+  NSFRB_HIP_TRY(hipSetDevice(c->device));
+  NSFRB_HIP_TRY(hipDeviceSynchronize());
+  const float* body = reinterpret_cast<const float*>(static_cast<const unsigned char*>(host_in) + sizeof h);
+  const size_t nb = sizeof(float) * kL.total;
+  NSFRB_HIP_TRY(hipMemcpy(c->d_theta, body, nb, hipMemcpyHostToDevice));
+  NSFRB_HIP_TRY(hipMemcpy(c->d_m, body + kL.total, nb, hipMemcpyHostToDevice));
+  NSFRB_HIP_TRY(hipMemcpy(c->d_v, body + 2 * kL.total, nb, hipMemcpyHostToDevice));
+  c->step = h.step;
+  c->cfg.lr = h.lr;
+  c->cfg.beta1 = h.beta1;
+  c->cfg.beta2 = h.beta2;
+  c->cfg.eps = h.eps;
+  c->weights_dirty = true;
+  if (user_counter) *user_counter = h.user_counter;
+  return NSFRB_OK;
+}
+
 extern "C" nsfrb_status nsfrb_classifier_set_lr(nsfrb_classifier* c, float lr) {
   host_clear_error();
   if (!c) return host_fail(NSFRB_ERR_INVALID_ARG, "classifier is NULL");
@@ -253,16 +338,12 @@ extern "C" nsfrb_status nsfrb_classifier_train_step(nsfrb_classifier* c, const v
   if (s != NSFRB_OK) return s;
   NSFRB_HIP_TRY(launch_head(c->d_h, d_labels, n, c->d_theta + kL.head, c->d_hs, c->d_grad + kL.head, c->d_dh, c->d_logits,
                             c->d_prob, c->d_loss, 1, st));
-  NSFRB_HIP_TRY(launch_pool_backward(c->d_dh, c->d_arg, c->d_act[3], n, npos, centre_pos(c), c->d_dpre[0], st));
-  int cur = 0;
+  NSFRB_HIP_TRY(launch_pool_backward(c->d_dh, c->d_arg, c->d_act[3], n, npos, centre_pos(c), c->d_dpre[3], st));
   for (int l = 3; l >= 0; --l) {
     const uint16_t* in = l ? c->d_act[l - 1] : x;
-    NSFRB_HIP_TRY(launch_conv_wgrad(kLayerCin[l], in, c->d_dpre[cur], c->d_part, c->d_part_db, c->d_grad + kL.w[l],
+    NSFRB_HIP_TRY(launch_conv_wgrad(kLayerCin[l], in, c->d_dpre[l], c->d_part, c->d_part_db, c->d_grad + kL.w[l],
                                     c->d_grad + kL.b[l], n, T, Y, st));
-    if (l) {
-      NSFRB_HIP_TRY(launch_conv_bwd_data(c->d_dpre[cur], c->d_wb[l], c->d_act[l - 1], c->d_dpre[cur ^ 1], n, T, Y, st));
-      cur ^= 1;
-    }
+    if (l) NSFRB_HIP_TRY(launch_conv_bwd_data(c->d_dpre[l], c->d_wb[l], c->d_act[l - 1], c->d_dpre[l - 1], n, T, Y, st));
   }
   if (update) {
     c->step += 1;
@@ -278,6 +359,42 @@ extern "C" nsfrb_status nsfrb_classifier_train_step(nsfrb_classifier* c, const v
     NSFRB_HIP_TRY(hipStreamSynchronize(st));
     *host_loss = c->h_loss[0];
   }
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_classifier_activations_get(nsfrb_classifier* c, int32_t layer, int32_t n,
+                                                          void* host_out) {
+  host_clear_error();
+  if (!c || !host_out) return host_fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  if (layer < 1 || layer > 4) return host_fail(NSFRB_ERR_INVALID_ARG, "layer must be 1..4");
+  if (n < 1 || n > c->cfg.max_batch) return host_fail(NSFRB_ERR_INVALID_ARG, "n must be 1..max_batch");
+  NSFRB_HIP_TRY(hipSetDevice(c->device));
+  NSFRB_HIP_TRY(hipDeviceSynchronize());
+  const size_t per = (size_t)c->cfg.n_time * c->cfg.ny * kX * kCh;
+  NSFRB_HIP_TRY(hipMemcpy(host_out, c->d_act[layer - 1], per * n * sizeof(uint16_t), hipMemcpyDeviceToHost));
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_classifier_grad_pre_get(nsfrb_classifier* c, int32_t layer, int32_t n,
+                                                       void* host_out) {
+  host_clear_error();
+  if (!c || !host_out) return host_fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  if (layer < 1 || layer > 4) return host_fail(NSFRB_ERR_INVALID_ARG, "layer must be 1..4");
+  if (n < 1 || n > c->cfg.max_batch) return host_fail(NSFRB_ERR_INVALID_ARG, "n must be 1..max_batch");
+  NSFRB_HIP_TRY(hipSetDevice(c->device));
+  NSFRB_HIP_TRY(hipDeviceSynchronize());
+  const size_t per = (size_t)c->cfg.n_time * c->cfg.ny * kX * kCh;
+  NSFRB_HIP_TRY(hipMemcpy(host_out, c->d_dpre[layer - 1], per * n * sizeof(uint16_t), hipMemcpyDeviceToHost));
+  return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_classifier_logits_get(nsfrb_classifier* c, int32_t n, float* host_out) {
+  host_clear_error();
+  if (!c || !host_out) return host_fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  if (n < 1 || n > c->cfg.max_batch) return host_fail(NSFRB_ERR_INVALID_ARG, "n must be 1..max_batch");
+  NSFRB_HIP_TRY(hipSetDevice(c->device));
+  NSFRB_HIP_TRY(hipDeviceSynchronize());
+  NSFRB_HIP_TRY(hipMemcpy(host_out, c->d_logits, sizeof(float) * n, hipMemcpyDeviceToHost));
   return NSFRB_OK;
 }
 

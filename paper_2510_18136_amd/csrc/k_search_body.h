@@ -360,6 +360,114 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
   __syncthreads();
 }
 
+
+// Global-to-LDS staging: row s of pixel p is n_t * sizeof(ST) bytes, a whole
+// number of 16-byte vectors; wave wv requests pieces wv, wv + NW, ... of
+// 64 vectors (one instruction each), lanes beyond the row's end disabled.
+// The loads land asynchronously; the caller waits (vmcnt) and synchronises.
+template <int NW>
+__device__ __forceinline__ void stage_rows_async(const CubeDesc& cd, int p, ST* buf, int wv, int l) {
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  const int rs = cd.rs, n_sub = cd.n_sub, n_t = cd.n_t;
+  const int row_vec = n_t * (int)sizeof(ST) / 16;   // 16-byte vectors per row
+  const int per_row = (row_vec + 63) / 64;
+  const unsigned char* zp = reinterpret_cast<const unsigned char*>(cd.z + (size_t)p * n_sub * n_t);
+  for (int i = wv; i < n_sub * per_row; i += NW) {
+    const int s = i / per_row, piece = i - s * per_row;
+    const int v = piece * 64 + l;
+    if (v < row_vec) {
+      const unsigned char* g = zp + ((size_t)s * n_t * sizeof(ST) + (size_t)v * 16);
+      unsigned char* d = reinterpret_cast<unsigned char*>(buf + (size_t)s * rs) + (size_t)piece * 1024;
+      __builtin_amdgcn_global_load_lds(g, (lds_ptr)d, 16, 0, 0);
+    }
+  }
+}
+
+// Between requesting a pixel's rows and waiting for them, a wave issues no
+// vector-memory load (the class table comes through the scalar cache, the S/N
+// normalisers are read once per kernel, trial validity comes from the table):
+// on gfx950 one counter tracks all vector-memory loads, so any load there
+// would wait for the row requests too.
+// ---------------------------------------------------------------------------
+// Persistent form of search_group for one pixel per workgroup: the workgroup
+// walks pixels blockIdx.x, blockIdx.x + gridDim.x, ...; its NW waves split the
+// DM trials round-robin as in search_group. When the layout allows, the rows of
+// the next pixel are requested with global-to-LDS loads as soon as no wave will
+// read the current rows again (after the last round's de-dispersion; with two
+// LDS buffers, at the start of the pixel), so those loads run under the boxcar
+// work. Delays and DM bounds come through the scalar cache and the S/N
+// normalisers are read once, so no vector-memory load is issued while row
+// requests are in flight (one counter tracks them all).
+// ---------------------------------------------------------------------------
+template <int C, int NW, int NBUF>
+__device__ __forceinline__ void search_persistent(const CubeDesc& cd, const int* __restrict__ delays,
+                                                  const int* __restrict__ dmaxv) {
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ Best red[NW];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int l = lane_id();
+  const int rs = cd.rs, n_sub = cd.n_sub, n_t = cd.n_t, n_pix = cd.n_pix, n_dm = cd.n_dm;
+  const int tile = n_sub * rs;
+  ST* bufs = reinterpret_cast<ST*>(lds_raw);
+  const ST neg = from_f32<ST>(kNegInf);
+  for (int i = threadIdx.x; i < NBUF * n_sub * (rs - n_t); i += 64 * NW) {
+    const int r = i / (rs - n_t);
+    bufs[r * rs + n_t + (i - r * (rs - n_t))] = neg;
+  }
+  const float norm_l = l < NSFRB_NW ? cd.norms[l] : 1.f;
+  const int n_rounds = (n_dm + NW - 1) / NW;
+  const int p_first = blockIdx.x;
+  if (p_first < n_pix) stage_rows_async<NW>(cd, p_first, bufs, wv, l);
+  int it = 0;
+  for (int p = p_first; p < n_pix; p += gridDim.x, ++it) {
+    ST* zl = bufs + (NBUF == 2 ? (it & 1) * tile : 0);
+    const int p_next = p + (int)gridDim.x;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (NBUF == 2 && p_next < n_pix) stage_rows_async<NW>(cd, p_next, bufs + ((it + 1) & 1) * tile, wv, l);
+    Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, n_pix}, p, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0, norm_l};
+    // The DM loop has no branches (a branch around the boxcar chain costs it
+    // registers): waves past the last trial repeat it (writing the same values
+    // twice), and a trial with no valid sample is searched with zero delays
+    // (row `delays` holds zeros for it) and then reported as -inf / -1.
+    for (int rd = 0; rd < n_rounds; ++rd) {
+      const int d = min(rd * NW + wv, n_dm - 1);
+      const int* dd = delays + (size_t)d * n_sub;
+      for (int pass = 0; pass < NSFRB_NPASS; ++pass) {
+        float cur[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) cur[c] = 0.f;
+        for (int s = 0; s < n_sub; ++s) add_row<C>(cur, zl + s * rs, dd[s], l);
+        if (NBUF == 1 && pass == NSFRB_NPASS - 1 && rd == n_rounds - 1) {
+          __syncthreads();   // no wave reads the rows of p again
+          if (p_next < n_pix) stage_rows_async<NW>(cd, p_next, bufs, wv, l);
+        }
+        nsfrb_chain<C>(pass, cur, rep);
+      }
+      // (read after the chain: a scalar held across it would push the chain's
+      // ballot masks out of scalar registers)
+      const bool searched = dmaxv[d] < n_t;
+      rep.d = d;
+      rep.snr_lane = searched ? rep.snr_lane : kNegInf;
+      rep.toa_lane = searched ? rep.toa_lane : -1;
+      rep.flush();
+    }
+    if (l == 0) red[wv] = rep.best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      Best b = red[0];
+      for (int w = 1; w < NW; ++w)
+        if (better(red[w].s, red[w].d, red[w].w, b)) b = red[w];
+      const bool ok = b.s > kNegInf;
+      cd.best_s[p] = ok ? b.s : kNegInf;
+      cd.best_d[p] = ok ? b.d : -1;
+      cd.best_w[p] = ok ? b.w : -1;
+      cd.best_t[p] = ok ? b.t : -1;
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
 }  // namespace nsfrb
 
 // Single cube: work item i covers pixels [i*PIX, i*PIX + PIX); items are dealt

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <tuple>
 #include <cmath>
 #include <cstdio>
@@ -297,8 +298,13 @@ static const char* store_type_name(int store) {
 
 // Translation unit with single-cube kernels for (C, PIX) pairs and, if
 // `batch` is set, the persistent batch kernel dispatching over `classes`.
+// A persistent kernel to instantiate: samples per lane, waves, LDS buffers.
+struct PersistentKernel {
+  int C, NW, n_buf;
+};
 static std::string gen_source(int store, int nw, int npass, const std::string& chain,
-                              const std::vector<KernelClass>& single, const std::vector<KernelClass>& batch) {
+                              const std::vector<KernelClass>& single, const std::vector<KernelClass>& batch,
+                              const std::vector<PersistentKernel>& persistent = {}) {
   std::ostringstream o;
   o << "#define NSFRB_RTC_PROLOGUE 1\n#include \"device_common.h\"\n";
   o << "#define NSFRB_NPASS " << npass << "\n";
@@ -309,6 +315,10 @@ static std::string gen_source(int store, int nw, int npass, const std::string& c
   for (const auto& k : single)
     o << "extern \"C\" __global__ __launch_bounds__(" << 64 * k.NW << ") void " << single_kernel_name(k)
       << "(nsfrb::CubeDesc cd) { search_cube<" << k.C << ", " << k.PIX << ", " << k.NW << ">(cd); }\n";
+  for (const auto& k : persistent)
+    o << "extern \"C\" __global__ __launch_bounds__(" << 64 * k.NW << ") void nsfrb_persistent_c" << k.C << "_w"
+      << k.NW << "_b" << k.n_buf << "(nsfrb::CubeDesc cd, const int* __restrict__ delays, const int* __restrict__ dmax"
+      << ") { search_persistent<" << k.C << ", " << k.NW << ", " << k.n_buf << ">(cd, delays, dmax); }\n";
   // one persistent kernel per class of the batch: its workgroups take the work
   // items of that class's cubes (descriptors contiguous, item_begin relative)
   // from a device counter, one item at a time, until the counter passes n_items
@@ -425,6 +435,45 @@ static std::vector<KernelClass> plan_candidates(int C, int n_dm, int n_sub, int 
   return out;
 }
 
+// ------------------------------------------------ persistent kernel plans
+// The persistent kernel keeps one pixel per workgroup of NW waves (DM trials
+// round-robin, as the per-DM kernel) and walks pixels blockIdx.x, +gridDim.x,
+// ...; the next pixel's rows are requested with global-to-LDS loads while the
+// current one is searched. Rows are whole 16-byte vectors (n_t * store bytes a
+// multiple of 16, pitch padded to 16 bytes); two LDS buffers when they fit.
+struct PersistentPlan {
+  int NW = 16, rs = 0, n_buf = 1;
+  size_t lds = 0;
+};
+
+static bool plan_persistent(int n_sub, int n_t, int C, int dmax_search, int store, int NW, PersistentPlan& out) {
+  out = PersistentPlan{};
+  out.NW = NW;
+  if (((size_t)n_t * dtype_size(store)) % 16 != 0) return false;
+  const int align = store == DT_F32 ? 4 : 8;
+  out.rs = (64 * C + dmax_search + 1 + align - 1) / align * align;
+  const size_t tile = (size_t)n_sub * out.rs * dtype_size(store);
+  if (2 * tile <= kLdsBudget) { out.n_buf = 2; out.lds = 2 * tile; }
+  else if (tile <= kLdsBudget) { out.n_buf = 1; out.lds = tile; }
+  else return false;
+  return true;
+}
+
+// 16 waves when there are at least 16 DM trials, and 8.
+static std::vector<PersistentPlan> persistent_candidates(int n_dm, int n_sub, int n_t, int C, int dmax_search,
+                                                         int store) {
+  std::vector<PersistentPlan> out;
+  for (int NW : {16, 8}) {
+    PersistentPlan pp;
+    if ((NW == 8 || n_dm >= NW) && plan_persistent(n_sub, n_t, C, dmax_search, store, NW, pp)) out.push_back(pp);
+  }
+  return out;
+}
+
+static std::string persistent_kernel_name(int C, const PersistentPlan& pp) {
+  return "nsfrb_persistent_c" + std::to_string(C) + "_w" + std::to_string(pp.NW) + "_b" + std::to_string(pp.n_buf);
+}
+
 // Host-only entry: generate (and optionally compile) the specialised search
 // source, for build checks and inspection. Not part of the public header.
 extern "C" int nsfrb_debug_plan_source(const nsfrb_search_config* cfg, char* out, int cap, int compile) {
@@ -446,7 +495,11 @@ extern "C" int nsfrb_debug_plan_source(const nsfrb_search_config* cfg, char* out
   if (const char* e = std::getenv("NSFRB_DEBUG_MAX_ACC")) max_acc = std::max(1, std::min(kMaxAccumulators, std::atoi(e)));
   if (gen_chain(std::vector<int>(cfg->width, cfg->width + cfg->n_width), chain, &npass, max_acc) != NSFRB_OK)
     return -1;
-  const std::string src = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, ks);
+  std::vector<PersistentKernel> pks;
+  for (const PersistentPlan& pp : persistent_candidates(cfg->n_dm, cfg->n_sub, cfg->n_time, C, dmax_search,
+                                                        cfg->store_dtype))
+    pks.push_back({C, pp.NW, pp.n_buf});
+  const std::string src = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, ks, pks);
   if (out && cap > 0) std::snprintf(out, (size_t)cap, "%s", src.c_str());
   if (compile) {
     std::vector<char> code;
@@ -469,6 +522,14 @@ struct nsfrb_search {
   hipFunction_t search_fn = nullptr;
   std::vector<KernelClass> tuned;      // candidates timed by the autotuner
   std::vector<float> tuned_ms;
+  // persistent kernels that compiled without spills, their persistent grids and
+  // tuned times; `pers` is the one in use (-1: the per-DM kernel above)
+  std::vector<PersistentPlan> pers_plans;
+  std::vector<hipFunction_t> pers_fns;
+  std::vector<unsigned> pers_grids;
+  std::vector<float> pers_ms;
+  int pers = -1;
+  int32_t* d_delays_zeroed = nullptr;  // delays with zero rows for trials that have no valid sample
   // device buffers
   int32_t *d_delays = nullptr, *d_dmax = nullptr;
   float* d_norms = nullptr;
@@ -505,6 +566,7 @@ static void release(nsfrb_search* h) {
                   h->d_count, h->d_cands, h->d_nout, h->d_flags};
   for (void* b : bufs)
     if (b) hipFree(b);
+  if (h->d_delays_zeroed) hipFree(h->d_delays_zeroed);
   if (h->h_cands) hipHostFree(h->h_cands);
   if (h->h_nout) hipHostFree(h->h_nout);
   if (h->done) hipEventDestroy(h->done);
@@ -549,12 +611,22 @@ extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfr
   // re-forming the de-dispersed series) before the configuration is refused.
   const int allowance = scratch_allowance();
   std::vector<KernelClass> usable;
+  // NSFRB_PERSISTENT: "0" per-DM kernel only; "NW" only the persistent kernel of NW waves (studies)
+  const char* pers_env = std::getenv("NSFRB_PERSISTENT");
+  const int pers_only = pers_env ? std::atoi(pers_env) : -1;
   for (int max_acc = kMaxAccumulators; max_acc >= 1 && usable.empty(); --max_acc) {
     std::string chain;
     int npass = 1;
     st = gen_chain(h->widths, chain, &npass, max_acc);
     if (st != NSFRB_OK) return st;
-    h->source = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, {});
+    std::vector<PersistentPlan> pps;
+    if (pers_only != 0)
+      for (const PersistentPlan& pp : persistent_candidates(cfg->n_dm, cfg->n_sub, cfg->n_time, h->C, dmax_search,
+                                                            cfg->store_dtype))
+        if (pers_only < 0 || pp.NW == pers_only) pps.push_back(pp);
+    std::vector<PersistentKernel> pks;
+    for (const PersistentPlan& pp : pps) pks.push_back({h->C, pp.NW, pp.n_buf});
+    h->source = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, {}, pks);
     st = load_module(h->device, h->source, &h->mod);
     if (st != NSFRB_OK) return st;
     for (const KernelClass& k : ks) {
@@ -563,6 +635,17 @@ extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfr
       int scratch = 0;
       HIP_TRY(hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn));
       if (scratch <= allowance) usable.push_back(k);
+    }
+    h->pers_plans.clear();
+    h->pers_fns.clear();
+    for (const PersistentPlan& pp : pps) {
+      hipFunction_t fn = nullptr;
+      HIP_TRY(hipModuleGetFunction(&fn, h->mod, persistent_kernel_name(h->C, pp).c_str()));
+      int scratch = 0;
+      HIP_TRY(hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, fn));
+      if (scratch > 0) continue;   // a spill reload would wait for the row requests in flight
+      h->pers_plans.push_back(pp);
+      h->pers_fns.push_back(fn);
     }
     h->max_acc = max_acc;
   }
@@ -605,6 +688,22 @@ extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfr
   HIP_TRY(hipMemcpy(h->d_dmax, h->dmaxv.data(), h->dmaxv.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->d_norms, norms.data(), norms.size() * sizeof(float), hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(h->d_flags, 0, sizeof(unsigned long long)));
+  {
+    std::vector<int32_t> dz(h->delays);
+    for (int d = 0; d < cfg->n_dm; ++d)
+      if (h->dmaxv[(size_t)d] >= cfg->n_time)
+        std::fill(dz.begin() + (long)d * cfg->n_sub, dz.begin() + (long)(d + 1) * cfg->n_sub, 0);
+    HIP_TRY(dalloc(&h->d_delays_zeroed, dz.size()));
+    HIP_TRY(hipMemcpy(h->d_delays_zeroed, dz.data(), dz.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  int n_cu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device));
+  for (size_t i = 0; i < h->pers_plans.size(); ++i) {
+    int per_cu = 0;
+    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, h->pers_fns[i], 64 * h->pers_plans[i].NW,
+                                                               h->pers_plans[i].lds));
+    h->pers_grids.push_back((unsigned)(std::max(1, n_cu) * std::max(1, per_cu)));
+  }
   st = autotune(h.get(), ks);
   if (st != NSFRB_OK) return st;
   h->lds_bytes = lds_bytes_for(h->pix, cfg->n_sub, h->rs, cfg->store_dtype);
@@ -655,24 +754,49 @@ static nsfrb_status launch_search_fn(const nsfrb_search* h, hipFunction_t fn, co
   return NSFRB_OK;
 }
 
-static nsfrb_status launch_search(const nsfrb_search* h, const void* z, hipStream_t st) {
+static nsfrb_status launch_persistent(const nsfrb_search* h, size_t i, const void* z, int n_pix, hipStream_t st) {
+  const PersistentPlan& pp = h->pers_plans[i];
+  CubeDescHost d = cube_desc(h, z, n_pix);
+  d.rs = pp.rs;
+  const int32_t* delays = h->d_delays_zeroed;
+  const int32_t* dmax = h->d_dmax;
+  void* args[] = {(void*)&d, (void*)&delays, (void*)&dmax};
+  const unsigned grid = (unsigned)std::min<long long>(h->pers_grids[i], std::max(1, n_pix));
+  HIP_TRY(hipModuleLaunchKernel(h->pers_fns[i], grid, 1, 1, 64 * pp.NW, 1, 1, (unsigned)pp.lds, st, args, nullptr));
+  return NSFRB_OK;
+}
+
+// The per-DM kernel the autotuner chose (the batch's separate launches use it too).
+static nsfrb_status launch_search_per_dm(const nsfrb_search* h, const void* z, hipStream_t st) {
   return launch_search_fn(h, h->search_fn, {h->C, h->pix, h->nw}, z, h->n_pix, st);
 }
 
-// Autotuner: time every pixels-per-workgroup candidate on this plan's shape
-// (the normalised-cube buffer, zeroed) and keep the fastest. Results are
-// cached per shape for the process. NSFRB_AUTOTUNE=0 keeps the heuristic
-// first candidate.
+static nsfrb_status launch_search(const nsfrb_search* h, const void* z, hipStream_t st) {
+  // the persistent kernel stages with global-to-LDS loads, which need a 16-byte aligned cube
+  if (h->pers >= 0 && (reinterpret_cast<uintptr_t>(z) & 15u) == 0)
+    return launch_persistent(h, (size_t)h->pers, z, h->n_pix, st);
+  return launch_search_per_dm(h, z, st);
+}
+
+// Autotuner: time every per-DM candidate (pixels and waves per workgroup) and
+// every persistent candidate (waves per workgroup) on this plan's shape (the
+// normalised-cube buffer, zeroed) and keep the fastest; all give bitwise equal
+// results. Choices are cached per shape for the process. NSFRB_AUTOTUNE=0
+// keeps the heuristic first per-DM candidate.
 struct TuneKey {
   int C, n_sub, n_t, n_dm, n_pix_bucket, store;
   std::vector<int32_t> widths;
+  std::vector<int32_t> pers_nw;
   bool operator<(const TuneKey& o) const {
-    return std::tie(C, n_sub, n_t, n_dm, n_pix_bucket, store, widths) <
-           std::tie(o.C, o.n_sub, o.n_t, o.n_dm, o.n_pix_bucket, o.store, o.widths);
+    return std::tie(C, n_sub, n_t, n_dm, n_pix_bucket, store, widths, pers_nw) <
+           std::tie(o.C, o.n_sub, o.n_t, o.n_dm, o.n_pix_bucket, o.store, o.widths, o.pers_nw);
   }
 };
+struct TuneChoice {
+  int pix, nw, pers_nw;   // pers_nw 0: the per-DM kernel is used
+};
 static std::mutex g_tune_mu;
-static std::map<TuneKey, std::pair<int, int>> g_tune_cache;   // (pixels, waves) per workgroup
+static std::map<TuneKey, TuneChoice> g_tune_cache;
 
 static nsfrb_status autotune(nsfrb_search* h, const std::vector<KernelClass>& ks) {
   const nsfrb_search_config& c = h->cfg;
@@ -680,25 +804,36 @@ static nsfrb_status autotune(nsfrb_search* h, const std::vector<KernelClass>& ks
   for (size_t i = 0; i < ks.size(); ++i)
     HIP_TRY(hipModuleGetFunction(&fns[i], h->mod, single_kernel_name(ks[i]).c_str()));
   auto choose = [&](size_t i) { h->pix = ks[i].PIX; h->nw = ks[i].NW; h->search_fn = fns[i]; };
+  auto choose_pers = [&](int nw) {
+    h->pers = -1;
+    for (size_t i = 0; i < h->pers_plans.size(); ++i)
+      if (h->pers_plans[i].NW == nw) h->pers = (int)i;
+  };
   choose(0);
-  // NSFRB_PLAN="pixels,waves" picks that shape when it is a candidate (for tuning studies)
+  h->pers = -1;
+  // NSFRB_PLAN="pixels,waves" picks that per-DM shape when it is a candidate (for tuning studies)
   if (const char* plan = std::getenv("NSFRB_PLAN")) {
     int pp = 0, ww = 0;
     if (std::sscanf(plan, "%d,%d", &pp, &ww) == 2)
       for (size_t i = 0; i < ks.size(); ++i)
         if (ks[i].PIX == pp && ks[i].NW == ww) { choose(i); return NSFRB_OK; }
   }
+  // NSFRB_PERSISTENT=NW (NW > 0) keeps that persistent kernel (for studies)
+  if (const char* pe = std::getenv("NSFRB_PERSISTENT"))
+    if (std::atoi(pe) > 0 && !h->pers_plans.empty()) { h->pers = 0; return NSFRB_OK; }
   const char* env = std::getenv("NSFRB_AUTOTUNE");
-  if (ks.size() == 1 || (env && std::atoi(env) == 0)) return NSFRB_OK;
+  if ((ks.size() == 1 && h->pers_plans.empty()) || (env && std::atoi(env) == 0)) return NSFRB_OK;
   int bucket = 0;
   while ((1 << bucket) < h->n_pix) ++bucket;
-  TuneKey key{h->C, c.n_sub, c.n_time, c.n_dm, bucket > 13 ? 13 : bucket, c.store_dtype, h->widths};
+  TuneKey key{h->C, c.n_sub, c.n_time, c.n_dm, bucket > 13 ? 13 : bucket, c.store_dtype, h->widths, {}};
+  for (const PersistentPlan& pp : h->pers_plans) key.pers_nw.push_back(pp.NW);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
       for (size_t i = 0; i < ks.size(); ++i)
-        if (ks[i].PIX == it->second.first && ks[i].NW == it->second.second) choose(i);
+        if (ks[i].PIX == it->second.pix && ks[i].NW == it->second.nw) choose(i);
+      choose_pers(it->second.pers_nw);
       return NSFRB_OK;
     }
   }
@@ -714,14 +849,19 @@ static nsfrb_status autotune(nsfrb_search* h, const std::vector<KernelClass>& ks
   HIP_TRY(hipEventCreate(&e1));
   // candidates are timed in interleaved rounds and each keeps its best round, so
   // clock ramp-up after an idle spell (e.g. the plan compile) favours none of them
-  std::vector<float> ms_best(ks.size(), 1e30f);
+  const size_t n_all = ks.size() + h->pers_plans.size();
+  auto launch = [&](size_t i) {
+    return i < ks.size() ? launch_search_fn(h, fns[i], ks[i], zt, n_tune, nullptr)
+                         : launch_persistent(h, i - ks.size(), zt, n_tune, nullptr);
+  };
+  std::vector<float> ms_best(n_all, 1e30f);
   for (int round = 0; round < 3; ++round) {
-    for (size_t i = 0; i < ks.size(); ++i) {
-      nsfrb_status st = launch_search_fn(h, fns[i], ks[i], zt, n_tune, nullptr);   // warm-up
+    for (size_t i = 0; i < n_all; ++i) {
+      nsfrb_status st = launch(i);   // warm-up
       if (st != NSFRB_OK) return st;
       HIP_TRY(hipEventRecord(e0, nullptr));
       for (int r = 0; r < 2; ++r) {
-        st = launch_search_fn(h, fns[i], ks[i], zt, n_tune, nullptr);
+        st = launch(i);
         if (st != NSFRB_OK) return st;
       }
       HIP_TRY(hipEventRecord(e1, nullptr));
@@ -737,10 +877,13 @@ static nsfrb_status autotune(nsfrb_search* h, const std::vector<KernelClass>& ks
     h->tuned_ms.push_back(ms_best[i]);
     if (ms_best[i] < best_ms) { best_ms = ms_best[i]; choose(i); }
   }
+  h->pers_ms.assign(ms_best.begin() + (long)ks.size(), ms_best.end());
+  for (size_t i = 0; i < h->pers_plans.size(); ++i)
+    if (h->pers_ms[i] < best_ms) { best_ms = h->pers_ms[i]; h->pers = (int)i; }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune_cache[key] = {h->pix, h->nw};
+  g_tune_cache[key] = {h->pix, h->nw, h->pers >= 0 ? h->pers_plans[(size_t)h->pers].NW : 0};
   return NSFRB_OK;
 }
 
@@ -920,11 +1063,17 @@ extern "C" nsfrb_status nsfrb_stage_times_get(nsfrb_search* h, float* ms3) {
 extern "C" nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* info) {
   g_last_error.clear();
   if (!h || !info) return fail(NSFRB_ERR_INVALID_ARG, "NULL argument");
+  const bool pe = h->pers >= 0;
+  const PersistentPlan* pp = pe ? &h->pers_plans[(size_t)h->pers] : nullptr;
   info[0] = h->C;
-  info[1] = h->pix;
-  info[2] = h->rs;
-  info[3] = (int32_t)h->lds_bytes;
-  info[4] = 64 * h->nw;
+  info[1] = pe ? 1 : h->pix;
+  info[2] = pe ? pp->rs : h->rs;
+  info[3] = (int32_t)(pe ? pp->lds : h->lds_bytes);
+  info[4] = 64 * (pe ? pp->NW : h->nw);
+  info[5] = pe ? 1 : 0;
+  info[6] = pe ? pp->n_buf : 0;
+  info[7] = pe ? (int32_t)h->pers_grids[(size_t)h->pers] : 0;
+  info[8] = 0;
   return NSFRB_OK;
 }
 
@@ -1183,7 +1332,7 @@ extern "C" nsfrb_status nsfrb_batch_run_separate(nsfrb_batch* b, const void* con
   nsfrb_status s = batch_stats(b, d_cubes, st);
   if (s != NSFRB_OK) return s;
   for (auto* h : b->cubes) {
-    s = launch_search(h, h->last_z, st);
+    s = launch_search_per_dm(h, h->last_z, st);
     if (s != NSFRB_OK) return s;
   }
   s = batch_candidates(b, st);

@@ -1,9 +1,11 @@
 // PSF-based reduction of an image's top candidates to the most likely one
 // (paper section 2.3): the simulated PSF, thresholded at a percentile, is a
 // binary mask centred on each candidate in turn; the other candidates inside
-// it are that candidate's possible sidelobes; the candidate whose weighted mean
+// it are that candidate's possible sidelobes; the candidate whose weighted-mean
 // S/N over itself and those sidelobes is largest is kept. Weights are the PSF's
-// amplitude at each member's offset, the PSF normalised to its centre.
+// amplitude at each member's offset, the PSF normalised to its centre; the
+// weighted mean of unit-noise S/N values, divided by its own noise, is
+// sum(w S) / sqrt(sum(w^2)), which a point source maximises on its own pixel.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -43,7 +45,7 @@ extern "C" nsfrb_status nsfrb_psf_reduce(const nsfrb_candidate* cands, int32_t n
   int best = -1;
   double best_s = -INFINITY;
   for (int i = 0; i < n; ++i) {
-    double num = cands[i].snr, den = 1.0;
+    double num = cands[i].snr, w2 = 1.0;
     for (int j = 0; j < n; ++j) {
       if (j == i) continue;
       const int dx = cands[j].x - cands[i].x, dy = cands[j].y - cands[i].y;
@@ -52,10 +54,10 @@ extern "C" nsfrb_status nsfrb_psf_reduce(const nsfrb_candidate* cands, int32_t n
       if (pv >= q) {
         const double w = pv / centre;
         num += w * (double)cands[j].snr;
-        den += w;
+        w2 += w * w;
       }
     }
-    const double s = num / den;
+    const double s = num / std::sqrt(w2);
     if (s > best_s) {
       best = i;
       best_s = s;

@@ -36,7 +36,8 @@ EXPORTS = [
     "nsfrb_generate_noise", "nsfrb_inject_boxcar", "nsfrb_inject_boxcars", "nsfrb_inject_boxcars_static", "nsfrb_philox_fill", "nsfrb_inject_rfi",
     "nsfrb_classifier_param_count", "nsfrb_classifier_create", "nsfrb_classifier_destroy",
     "nsfrb_classifier_params_get", "nsfrb_classifier_params_set", "nsfrb_classifier_set_lr",
-    "nsfrb_classifier_grads_get",
+    "nsfrb_classifier_grads_get", "nsfrb_classifier_state_bytes", "nsfrb_classifier_save", "nsfrb_classifier_load",
+    "nsfrb_classifier_activations_get", "nsfrb_classifier_grad_pre_get", "nsfrb_classifier_logits_get",
     "nsfrb_classifier_train_step", "nsfrb_classifier_infer", "nsfrb_cutouts_extract",
     "nsfrb_bin_time", "nsfrb_multiscale_create", "nsfrb_multiscale_destroy", "nsfrb_multiscale_run",
     "nsfrb_multiscale_scale", "nsfrb_multiscale_candidates_get", "nsfrb_plan_dm_grid",
@@ -150,6 +151,13 @@ def lib():
             "nsfrb_inject_boxcars_static": ([ctypes.POINTER(vp), i32, i32, i32, i32, i32, i32,
                                              ctypes.POINTER(Boxcar), pi32, i32, vp], ctypes.c_int),
             "nsfrb_philox_fill": ([vp, ctypes.c_int64, ctypes.c_uint64, vp], ctypes.c_int),
+            "nsfrb_classifier_state_bytes": ([], ctypes.c_int64),
+            "nsfrb_classifier_save": ([vp, ctypes.c_uint64, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
+                                      ctypes.c_int),
+            "nsfrb_classifier_load": ([vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+            "nsfrb_classifier_activations_get": ([vp, i32, i32, vp], ctypes.c_int),
+            "nsfrb_classifier_grad_pre_get": ([vp, i32, i32, vp], ctypes.c_int),
+            "nsfrb_classifier_logits_get": ([vp, i32, pf], ctypes.c_int),
             "nsfrb_inject_rfi": ([vp, i32, i32, i32, i32, i32, i32, i32, i32, i32, ctypes.c_float, vp], ctypes.c_int),
             "nsfrb_classifier_param_count": ([], ctypes.c_int32),
             "nsfrb_classifier_create": ([ctypes.POINTER(ClassifierConfig), ctypes.POINTER(vp)], ctypes.c_int),
@@ -513,10 +521,11 @@ class Search:
         return out
 
     def plan_info(self):
-        out = np.zeros(5, np.int32)
+        out = np.zeros(9, np.int32)
         check(lib().nsfrb_search_plan_info(self.h, _ptr(out, ctypes.c_int32)))
         return dict(samples_per_lane=int(out[0]), pixels_per_workgroup=int(out[1]), row_len=int(out[2]),
-                    lds_bytes=int(out[3]), threads_per_workgroup=int(out[4]))
+                    lds_bytes=int(out[3]), threads_per_workgroup=int(out[4]), persistent=bool(out[5]),
+                    lds_buffers=int(out[6]), workgroups=int(out[7]))
 
 
 class Batch:
@@ -687,6 +696,49 @@ class Classifier:
         out = np.zeros(self.n_params, np.float32)
         check(lib().nsfrb_classifier_grads_get(self.h, _ptr(out, ctypes.c_float)))
         return out
+
+    def activations(self, layer, n):
+        """BF16 output of conv layer 1..4 from the last forward pass, as float32 [n][T][Y][32][32]."""
+        c = self.cfg
+        bits = np.zeros(n * c.n_time * c.ny * 32 * 32, np.uint16)
+        check(lib().nsfrb_classifier_activations_get(self.h, int(layer), int(n), _ptr(bits, ctypes.c_uint16)))
+        return (bits.astype(np.uint32) << 16).view(np.float32).reshape(n, c.n_time, c.ny, 32, 32)
+
+    def grad_pre(self, layer, n):
+        """BF16 gradient at conv layer 1..4's pre-activation from the last train step, float32 [n][T][Y][32][32]."""
+        c = self.cfg
+        bits = np.zeros(n * c.n_time * c.ny * 32 * 32, np.uint16)
+        check(lib().nsfrb_classifier_grad_pre_get(self.h, int(layer), int(n), _ptr(bits, ctypes.c_uint16)))
+        return (bits.astype(np.uint32) << 16).view(np.float32).reshape(n, c.n_time, c.ny, 32, 32)
+
+    def logits(self, n):
+        out = np.zeros(n, np.float32)
+        check(lib().nsfrb_classifier_logits_get(self.h, int(n), _ptr(out, ctypes.c_float)))
+        return out
+
+    def state(self, user_counter=0):
+        """Checkpoint bytes: weights, Adam moments, step count, optimiser settings, user_counter."""
+        n = int(lib().nsfrb_classifier_state_bytes())
+        buf = np.zeros(n, np.uint8)
+        written = ctypes.c_int64(0)
+        check(lib().nsfrb_classifier_save(self.h, ctypes.c_uint64(int(user_counter)), _ptr(buf, ctypes.c_uint8), n,
+                                          ctypes.byref(written)))
+        return buf.tobytes()
+
+    def load_state(self, blob):
+        """Restore a checkpoint from state(); returns its user_counter."""
+        b = np.frombuffer(bytes(blob), np.uint8)
+        ctr = ctypes.c_uint64(0)
+        check(lib().nsfrb_classifier_load(self.h, _ptr(b, ctypes.c_uint8), b.size, ctypes.byref(ctr)))
+        return int(ctr.value)
+
+    def save(self, path, user_counter=0):
+        with open(path, "wb") as f:
+            f.write(self.state(user_counter))
+
+    def load(self, path):
+        with open(path, "rb") as f:
+            return self.load_state(f.read())
 
     def train_step(self, d_cutouts, d_labels, n, update=True, stream=0, want_loss=True):
         loss = ctypes.c_float(float("nan"))

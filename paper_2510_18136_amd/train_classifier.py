@@ -30,7 +30,12 @@ pixels, the two highest-S/N pixels of a sky cube away from every injection
 plus one random such pixel, and eight random pixels of every RFI cube).
 
 Training is one pass over freshly generated cutouts (batch 64, Adam, the
-learning rate following a cosine from lr to lr/100).
+learning rate following a cosine from lr to lr/100). The generator is
+counter-based: round r of cubes draws from a NumPy generator seeded with
+(seed, r), so a run checkpointed after round r (weights, Adam state and step
+count through the library's checkpoint, the round counter in its user word,
+the cutout and step counts beside it) resumes with the result it would have
+had without the stop.
 
 The plain S/N >= 6 threshold is the baseline and the fallback: evaluate()
 reports its recall and false candidates next to the classifier's. The
@@ -158,10 +163,11 @@ def candidate_records(rng, k, plan, snr, dmi, toa):
 class CutoutSource:
     """Labelled candidate cutouts generated and searched on the GPU."""
 
-    def __init__(self, seed, n_cubes=16, device=0):
+    def __init__(self, seed, n_cubes=16, device=0, first_round=0):
         torch = _torch()
         self.torch = torch
-        self.rng = np.random.default_rng(seed)
+        self.seed = seed
+        self.rounds = first_round           # rounds generated so far (the generator's counter)
         self.n_cubes = n_cubes
         self.cfg = nsfrb.SearchConfig(NX, NY, NT, FREQS, DMS, WIDTHS, in_dtype="f32", store_dtype="f16",
                                       norm="pixel_subband", snr_threshold=0.0, max_candidates=16, device=device)
@@ -171,7 +177,8 @@ class CutoutSource:
 
     def round(self):
         """Generate and search n_cubes cubes; returns (z pointers, candidate records)."""
-        rng, torch = self.rng, self.torch
+        rng, torch = np.random.default_rng([self.seed, self.rounds]), self.torch
+        self.rounds += 1
         kinds = rng.choice(["sky", "spike", "stripe"], size=self.n_cubes, p=[0.6, 0.2, 0.2])
         ptrs = [int(self.raw[k].data_ptr()) for k in range(self.n_cubes)]
         plans = [plan_cube(rng, k, str(kinds[k])) for k in range(self.n_cubes)]
@@ -200,20 +207,33 @@ def _extract(clf, src, zptrs, recs, out):
     clf.cutouts(zptrs, "f16", NX, NY, N_SUB, NT, src.delays, [r[:5] for r in recs], out.data_ptr())
 
 
-def train(clf, n_train, seed, lr=1e-3, batch=64, n_cubes=16, log=print):
+def train(clf, n_train, seed, lr=1e-3, batch=64, n_cubes=16, log=print, ckpt=None, resume=False,
+          stop_after_rounds=None):
+    """One pass over n_train fresh cutouts. With `ckpt` (a path), a checkpoint is
+    written after every round of cubes (ckpt, plus ckpt + '.json' with the
+    cutout and step counts); resume=True continues from it. stop_after_rounds
+    ends the run early after that many rounds (a stopped job, for tests)."""
     torch = _torch()
-    src = CutoutSource(seed, n_cubes)
+    seen, steps, losses, first_round = 0, 0, [], 0
+    if resume:
+        first_round = clf.load(ckpt)
+        with open(ckpt + ".json") as f:
+            meta = json.load(f)
+        seen, steps, losses = meta["seen"], meta["steps"], [tuple(x) for x in meta["losses"]]
+        assert meta["rounds"] == first_round
+    src = CutoutSource(seed, n_cubes, first_round=first_round)
     xbuf = torch.empty((batch, CUT_T, 32, 32, N_SUB), dtype=torch.int16, device="cuda")
     ybuf = torch.empty(batch, dtype=torch.float32, device="cuda")
-    rng = np.random.default_rng(seed + 17)
-    seen, steps, losses = 0, 0, []
     t_gen = t_step = 0.0
     t_start = time.time()
     while seen < n_train:
+        if stop_after_rounds is not None and src.rounds >= stop_after_rounds:
+            break
         t0 = time.time()
+        r = src.rounds
         zptrs, recs = src.round()
         t_gen += time.time() - t0
-        order = rng.permutation(len(recs))
+        order = np.random.default_rng([seed + 17, r]).permutation(len(recs))
         for i in range(0, len(order), batch):
             if seen >= n_train:
                 break
@@ -230,6 +250,11 @@ def train(clf, n_train, seed, lr=1e-3, batch=64, n_cubes=16, log=print):
             t_step += time.time() - t1
             seen += len(sel)
             steps += 1
+        if ckpt:
+            torch.cuda.synchronize()
+            clf.save(ckpt, user_counter=src.rounds)
+            with open(ckpt + ".json", "w") as f:
+                json.dump(dict(rounds=src.rounds, seen=seen, steps=steps, losses=losses), f)
     torch.cuda.synchronize()
     src.close()
     return dict(cutouts=seen, steps=steps, seconds=time.time() - t_start, search_gen_seconds=t_gen,
@@ -310,11 +335,13 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--out", default="classifier_run")
+    ap.add_argument("--resume", action="store_true", help="continue from <out>/checkpoint.bin")
     a = ap.parse_args(argv)
     _torch()                     # torch's HIP runtime first, then the library (one runtime per process)
     os.makedirs(a.out, exist_ok=True)
     with nsfrb.Classifier(max_batch=a.batch, n_time=CUT_T, ny=32, lr=a.lr, seed=a.seed) as clf:
-        tr = train(clf, a.train, seed=a.seed * 1000 + 1, lr=a.lr, batch=a.batch, log=lambda m: print(m, flush=True))
+        tr = train(clf, a.train, seed=a.seed * 1000 + 1, lr=a.lr, batch=a.batch, log=lambda m: print(m, flush=True),
+                   ckpt=os.path.join(a.out, "checkpoint.bin"), resume=a.resume)
         np.save(os.path.join(a.out, "params.npy"), clf.params())
         print(f"[train] done: {tr['cutouts']} cutouts in {tr['seconds']:.1f}s", flush=True)
         val = score(clf, a.val, seed=a.seed * 1000 + 2, batch=a.batch)

@@ -226,7 +226,7 @@ def test_psf_reduce_hand_case_and_errors(L):
     p = np.zeros((5, 5), np.float32)
     p[2, 2], p[2, 4], p[2, 0], p[0, 2], p[4, 2] = 1.0, 0.5, 0.5, 0.25, 0.25
     i, s = nsfrb.psf_reduce([dict(x=10, y=10, snr=8.0), dict(x=12, y=10, snr=6.0), dict(x=10, y=12, snr=7.0)], p)
-    assert i == 0 and s == pytest.approx(11.0 / 1.5)
+    assert i == 0 and s == pytest.approx(11.0 / np.sqrt(1.25))
     for bad, pct in ((np.zeros((4, 5), np.float32), 90.0), (p, 120.0), (np.zeros((5, 5), np.float32), 90.0)):
         with pytest.raises(nsfrb.NsfrbError) as e:
             nsfrb.psf_reduce([dict(x=0, y=0, snr=7.0)], bad, pct)

@@ -147,3 +147,115 @@ def test_memorises_a_small_batch():
         for _ in range(60):
             last = c.train_step(xd.data_ptr(), yd.data_ptr(), n, stream=st)
     assert np.isfinite(first) and last < 0.2 * first
+
+
+U_F32 = 2.0 ** -24          # FP32 unit roundoff
+
+
+def bf16_ulp(v):
+    """Spacing of BF16 numbers at |v|: 2^(floor(log2 |v|) - 7) (0 for v = 0)."""
+    a = np.abs(v)
+    return np.where(a > 0, np.exp2(np.floor(np.log2(np.maximum(a, 1e-300))) - 7), 0.0)
+
+
+def rounding_bound(terms):
+    """Worst-case error of an FP32 sum of `terms` products: terms * u * sum|products|."""
+    return terms * U_F32
+
+
+def check_rounded(name, got, ref, abs_sum, terms, min_equal=0.999):
+    """got = BF16(FP32 sum), ref = BF16(FP64 sum) of the same inputs: they may
+    differ only where the sum lies within the FP32 error of a BF16 rounding
+    boundary, by at most one BF16 spacing plus that error."""
+    d = np.abs(got - ref)
+    allow = bf16_ulp(np.maximum(np.abs(got), np.abs(ref))) + rounding_bound(terms) * abs_sum
+    equal = float((got == ref).mean())
+    print(f"{name}: bit-equal {equal:.5f}, max |d| {d.max():.3e}, worst d/allow {(d / np.maximum(allow, 1e-300)).max():.3f}",
+          flush=True)
+    assert (d <= allow).all(), name
+    assert equal >= min_equal, name
+
+
+def test_real_cutout_shape_layer_by_layer():
+    """The workload's cutout shape (64 x 32 x 32 x 16, two cutouts), so the conv
+    row blocks beyond the first (and their halos) and the full pooling pass run.
+
+    Each stage is checked element by element against the FP64 oracle fed with
+    the GPU's own inputs to that stage (a flip in one layer would otherwise
+    cascade into the next): every conv layer's BF16 output, every back-propagated
+    BF16 pre-activation gradient, every weight and bias gradient, the logits of
+    training and of inference, and the probabilities. The bounds come from the
+    arithmetic: one BF16 spacing where the GPU's FP32 sum and the oracle's FP64
+    sum round differently, plus the worst-case FP32 error of the sum
+    (terms x 2^-24 x sum of |products|, computed by the oracle on absolute
+    values). The end-to-end activations (oracle on its own inputs throughout)
+    are reported, their flips cascading through the layers."""
+    n, T, Y = 2, 64, 32
+    x, theta, labels = make_case(11, n=n, T=T, Y=Y)
+    P = cnn.unpack(theta)
+    with nsfrb.Classifier(max_batch=n, n_time=T, ny=Y, lr=0.0) as c:
+        c.set_params(theta)
+        xd = bf16_device(x)
+        yd = torch.from_numpy(labels.astype(np.float32)).cuda()
+        print(f"[gpu] classifier at the real cutout shape n={n} T={T} Y={Y}", flush=True)
+        c.train_step(xd.data_ptr(), yd.data_ptr(), n, update=False, want_loss=False,
+                     stream=torch.cuda.current_stream().cuda_stream)
+        g = c.grads().astype(np.float64)
+        acts = [cnn.bf16(x)] + [c.activations(l, n).astype(np.float64) for l in range(1, 5)]
+        dpre = [None] + [c.grad_pre(l, n).astype(np.float64) for l in range(1, 5)]
+        z_train = c.logits(n).astype(np.float64)
+        prob = torch.zeros(n, device="cuda")
+        c.infer(xd.data_ptr(), n, prob.data_ptr(), stream=torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        p = prob.cpu().numpy().astype(np.float64)
+        z_inf = c.logits(n).astype(np.float64)
+    print("[gpu] FP64 oracle, stage by stage on the GPU's inputs (about a minute)", flush=True)
+    # forward, layer by layer
+    for l in range(4):
+        W, b = cnn.bf16(P[2 * l]), P[2 * l + 1]
+        ref = cnn.bf16(np.maximum(cnn.conv3(acts[l], W, b), 0.0))
+        abs_sum = cnn.conv3(np.abs(acts[l]), np.abs(W), np.abs(b))
+        check_rounded(f"a{l + 1}", acts[l + 1], ref, abs_sum, 27 * W.shape[2] + 1)
+    # head on the GPU's a4: logits (training and inference) and probabilities
+    f = cnn.head_forward(theta, acts[4])
+    zb = 1e-5 * (1.0 + (np.abs(f["h"]) @ np.abs(P[8]).T + np.abs(P[9])) @ np.abs(P[10]) + abs(P[11][0]))
+    for name, z in (("train", z_train), ("infer", z_inf)):
+        dz = np.abs(z - f["z"])
+        print(f"logits ({name}): max |dz| {dz.max():.3e} (bound {zb.min():.3e})", flush=True)
+        assert (dz <= zb).all(), name
+    np.testing.assert_allclose(p, 1.0 / (1.0 + np.exp(-z_inf)), rtol=0, atol=1e-6)
+    # backward: the head's gradients and d(loss)/d(a4), then each layer on the GPU's pre-activation gradient
+    f["acts"] = acts
+    _, head_g, dpost = cnn.head_backward(theta, f, labels)
+    sl = dict(tensor_slices())
+    for name, ref in zip(("fc1.W", "fc1.b", "fc2.w", "fc2.b"), head_g):
+        d = np.abs(g[sl[name]] - ref.ravel())
+        allow = 1e-5 * (np.abs(ref.ravel()) + np.sqrt(np.mean(ref ** 2))) + 1e-9
+        print(f"{name:10s} max |d| {d.max():.3e}  worst d/allow {(d / allow).max():.3f}", flush=True)
+        assert (d <= allow).all(), name
+    # |d(loss)/d(a4)| bound: the head's backward on absolute values; 128 terms cover the FP32
+    # sums of the head (64 + 32) and the logit's own FP32 error entering sigmoid(z) - label
+    du_abs = np.abs(np.outer((1.0 / (1.0 + np.exp(-f["z"])) - labels) / n, P[10])) * (f["u"] > 0)
+    adpost = cnn.pool_backward(acts[4].shape, f["arg"], du_abs @ np.abs(P[8]))
+    check_rounded("dpre4", dpre[4], cnn.bf16(dpost * (acts[4] > 0)), adpost, 128)
+    for l in (3, 2, 1, 0):
+        W = cnn.bf16(P[2 * l])
+        dW, db, dx = cnn.conv3_backward(acts[l], W, dpre[l + 1], need_dx=l > 0)
+        aW, ab, adx = cnn.conv3_backward(np.abs(acts[l]), np.abs(W), np.abs(dpre[l + 1]), need_dx=l > 0)
+        n_pos = n * T * Y * 32
+        for name, got, ref, a in ((f"conv{l + 1}.W", g[sl[f"conv{l + 1}.W"]], dW.ravel(), aW.ravel()),
+                                  (f"conv{l + 1}.b", g[sl[f"conv{l + 1}.b"]], db.ravel(), ab.ravel())):
+            d = np.abs(got - ref)
+            allow = rounding_bound(n_pos) * a + 1e-12
+            print(f"{name:10s} max |d| {d.max():.3e}  max rel {(d / np.maximum(np.abs(ref), 1e-30)).max():.3e}  "
+                  f"worst d/allow {(d / allow).max():.3f}", flush=True)
+            assert (d <= allow).all(), name
+        if l > 0:
+            check_rounded(f"dpre{l}", dpre[l], cnn.bf16(dx * (acts[l] > 0)), adx, 27 * 32)
+    # end to end (the oracle on its own inputs throughout), for the record
+    _, g_ref, fo = cnn.loss_and_grad(theta, x, labels, bf16_points=True)
+    for l in range(1, 5):
+        print(f"end to end a{l}: bit-equal {float((acts[l] == fo['acts'][l]).mean()):.5f}", flush=True)
+    for name, s_ in tensor_slices():
+        rel = np.linalg.norm(g[s_] - g_ref[s_]) / max(np.linalg.norm(g_ref[s_]), 1e-30)
+        print(f"end to end {name:10s} relative L2 {rel:.3e}", flush=True)

@@ -27,10 +27,47 @@ def test_hand_worked_case():
     assert np.percentile(tiny_psf(), 90) == pytest.approx(0.4)
     cands = [(10, 10, 8.0), (12, 10, 6.0), (10, 12, 7.0)]
     i, s = postproc.psf_reduce(cands, tiny_psf())
-    # centre 0: member 1 at (+2, 0), weight 0.5 -> (8 + 3) / 1.5 = 7.333; member 2 at (0, +2) not in mask
-    # centre 1: member 0 at (-2, 0), weight 0.5 -> (6 + 4) / 1.5 = 6.667
+    # S/N of the weighted mean: sum(w S) / sqrt(sum(w^2))
+    # centre 0: member 1 at (+2, 0), weight 0.5 -> (8 + 3) / sqrt(1.25) = 9.839; member 2 at (0, +2) not in mask
+    # centre 1: member 0 at (-2, 0), weight 0.5 -> (6 + 4) / sqrt(1.25) = 8.944
     # centre 2: no members -> 7.0
-    assert i == 0 and s == pytest.approx(11.0 / 1.5)
+    assert i == 0 and s == pytest.approx(11.0 / np.sqrt(1.25))
+
+
+def test_weighted_mean_snr_is_the_snr_of_the_weighted_mean():
+    """Members with unit-noise S/N values: the score equals the weighted mean
+    divided by its standard deviation, checked against a Monte Carlo of noise-only
+    S/N values (the score of pure noise has unit variance)."""
+    p = tiny_psf()
+    cands = [(10, 10, 0.0), (12, 10, 0.0), (8, 10, 0.0)]      # centre 0 has two 0.5-weight members
+    rng = np.random.default_rng(4)
+    scores = []
+    for _ in range(4000):
+        s = rng.standard_normal(3)
+        c = [(x, y, float(v)) for (x, y, _), v in zip(cands, s)]
+        scores.append(((s[0] + 0.5 * s[1] + 0.5 * s[2]) / np.sqrt(1.5), postproc.psf_reduce(c, p)))
+    direct = np.array([a for a, _ in scores])
+    assert abs(direct.std() - 1.0) < 0.05
+    # whenever the first candidate wins, its score is that unit-noise statistic
+    for a, (i, s) in scores:
+        if i == 0:
+            assert s == pytest.approx(a, rel=1e-12)
+
+
+def test_point_source_beats_its_own_sidelobes():
+    """Candidates at a point source and at its brightest sidelobes, with S/N in
+    proportion to the beam: the source is kept, wherever the sidelobes are."""
+    psf = synth.snapshot_psf(half=20)
+    h = 20
+    order = np.argsort(psf.ravel())[::-1]
+    for s_c in (8.0, 15.0, 40.0):
+        cands = [(100, 100, s_c)]
+        for k in order[1:10]:                             # the nine brightest other beam pixels
+            dy, dx = divmod(int(k), psf.shape[1])
+            cands.append((100 + dx - h, 100 + dy - h, s_c * float(psf.ravel()[k])))
+        cands.sort(key=lambda c: -c[2])
+        i, _ = postproc.psf_reduce(cands, psf)
+        assert (cands[i][0], cands[i][1]) == (100, 100)
 
 
 def test_translation_invariance():
