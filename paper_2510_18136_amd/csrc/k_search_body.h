@@ -41,6 +41,20 @@ namespace nsfrb {
 
 constexpr float kNegInf = -__builtin_inff();
 
+// Work-item and workgroup indices read inline from the hardware registers and
+// the HSA dispatch packet. The generated kernels are compiled with IEEE mode
+// off, and the runtime's index accessors then stay out-of-line calls whose
+// results the compiler must treat as per-lane values.
+__device__ __forceinline__ int tid_x() { return (int)__builtin_amdgcn_workitem_id_x(); }
+__device__ __forceinline__ int wg_id() { return (int)__builtin_amdgcn_workgroup_id_x(); }
+// Workgroups in the launch: grid_size_x (work-items, a 32-bit field at byte 12
+// of the packet) over the workgroup size WG the kernel is launched with.
+template <int WG>
+__device__ __forceinline__ int n_wg() {
+  const auto* pk = (const __attribute__((address_space(4))) unsigned char*)__builtin_amdgcn_dispatch_ptr();
+  return (int)(*(const __attribute__((address_space(4))) unsigned int*)(pk + 12) / (unsigned)WG);
+}
+
 // Value of x held by lane l+1 (lane 63 reads 0). Only used where the sum it
 // feeds is already -inf for lane 63 (see shift_add).
 __device__ __forceinline__ float lane_next(float x) {
@@ -229,7 +243,8 @@ struct CubeDesc {
   int* best_d;
   int* best_w;
   int* best_t;
-  int n_pix, n_sub, n_t, n_dm, rs, cls;
+  int n_pix, n_sub, n_t, n_dm, rs;
+  int dma_w;                // batch row copy: global-to-LDS bytes per lane (16 or 4), else ordinary loads
   long long item_begin;     // first work item of this cube in a batch
 };
 
@@ -252,7 +267,7 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
   constexpr int WPP = NW / PIX;            // waves per pixel
   // the wave index is uniform across the wave; saying so lets every per-DM
   // value (delays, DM bounds) come through the scalar cache
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wv = __builtin_amdgcn_readfirstlane(tid_x() / kWave);
   const int l = lane_id();
   const int slot = wv / WPP;               // which pixel of the group
   const int wq = wv % WPP;                 // this wave's DM chunk: d = wq, wq + WPP, ...
@@ -274,16 +289,16 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
     if (vec) {
       const int nv = n_sub * n_t / VW;
       const uint4* src = reinterpret_cast<const uint4*>(zp);
-      for (int v0 = threadIdx.x; v0 < nv; v0 += kStageBatch * blockDim.x) {
+      for (int v0 = tid_x(); v0 < nv; v0 += kStageBatch * 64 * NW) {
         uint4 buf[kStageBatch];
 #pragma unroll
         for (int b = 0; b < kStageBatch; ++b) {
-          const int v = v0 + b * (int)blockDim.x;
+          const int v = v0 + b * 64 * NW;
           buf[b] = v < nv ? src[v] : make_uint4(0u, 0u, 0u, 0u);
         }
 #pragma unroll
         for (int b = 0; b < kStageBatch; ++b) {
-          const int v = v0 + b * (int)blockDim.x;
+          const int v = v0 + b * 64 * NW;
           if (v < nv) {
             const int e = v * VW, s = e / n_t, u = e - s * n_t;
             // FP32 samples are dwords; 16-bit rows have even pitches and u is a
@@ -297,7 +312,7 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
         }
       }
       const int tail = rs - n_t;
-      for (int i = threadIdx.x; i < n_sub * tail; i += blockDim.x) {
+      for (int i = tid_x(); i < n_sub * tail; i += 64 * NW) {
         const int s = i / tail;
         dstp[s * rs + n_t + (i - s * tail)] = neg;
       }
@@ -305,7 +320,7 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
       for (int s = 0; s < n_sub; ++s) {
         const ST* src = zp + (size_t)s * n_t;
         ST* dst = dstp + s * rs;
-        for (int u = threadIdx.x; u < rs; u += blockDim.x) dst[u] = (u < n_t) ? src[u] : neg;
+        for (int u = tid_x(); u < rs; u += 64 * NW) dst[u] = (u < n_t) ? src[u] : neg;
       }
     }
   }
@@ -345,8 +360,8 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
   }
   if (l == 0) red[wv] = rep.best;
   __syncthreads();
-  if (threadIdx.x < PIX && p0 + (int)threadIdx.x < cd.n_pix) {
-    const int k = threadIdx.x;
+  if (tid_x() < PIX && p0 + tid_x() < cd.n_pix) {
+    const int k = tid_x();
     Best b = red[k * WPP];
     for (int j = 1; j < WPP; ++j)
       if (better(red[k * WPP + j].s, red[k * WPP + j].d, red[k * WPP + j].w, b)) b = red[k * WPP + j];
@@ -365,22 +380,43 @@ __device__ __forceinline__ void search_group(const CubeDesc& cd, int p0, ST* zl,
 // number of 16-byte vectors; wave wv requests pieces wv, wv + NW, ... of
 // 64 vectors (one instruction each), lanes beyond the row's end disabled.
 // The loads land asynchronously; the caller waits (vmcnt) and synchronises.
-template <int NW>
+template <int NW, int W = 16>   // W: 16 or 4 bytes per lane
 __device__ __forceinline__ void stage_rows_async(const CubeDesc& cd, int p, ST* buf, int wv, int l) {
   typedef __attribute__((address_space(3))) void* lds_ptr;
   const int rs = cd.rs, n_sub = cd.n_sub, n_t = cd.n_t;
-  const int row_vec = n_t * (int)sizeof(ST) / 16;   // 16-byte vectors per row
-  const int per_row = (row_vec + 63) / 64;
+  const int row_bytes = n_t * (int)sizeof(ST);
+  const int per_row = (row_bytes + 64 * W - 1) / (64 * W);    // instructions per row
   const unsigned char* zp = reinterpret_cast<const unsigned char*>(cd.z + (size_t)p * n_sub * n_t);
   for (int i = wv; i < n_sub * per_row; i += NW) {
     const int s = i / per_row, piece = i - s * per_row;
-    const int v = piece * 64 + l;
-    if (v < row_vec) {
-      const unsigned char* g = zp + ((size_t)s * n_t * sizeof(ST) + (size_t)v * 16);
-      unsigned char* d = reinterpret_cast<unsigned char*>(buf + (size_t)s * rs) + (size_t)piece * 1024;
-      __builtin_amdgcn_global_load_lds(g, (lds_ptr)d, 16, 0, 0);
+    const int off = (piece * 64 + l) * W;                         // byte offset of this lane in the row
+    if (off < row_bytes) {
+      const unsigned char* g = zp + ((size_t)s * row_bytes + (size_t)off);
+      unsigned char* d = reinterpret_cast<unsigned char*>(buf + (size_t)s * rs) + (size_t)piece * 64 * W;
+      if constexpr (W == 16) __builtin_amdgcn_global_load_lds(g, (lds_ptr)d, 16, 0, 0);
+      else __builtin_amdgcn_global_load_lds(g, (lds_ptr)d, 4, 0, 0);
     }
   }
+}
+// Rows of pixel p into buf with ordinary loads and LDS stores (any alignment;
+// complete when the caller's barrier has passed).
+template <int NW>
+__device__ __forceinline__ void stage_rows_sync(const CubeDesc& cd, int p, ST* buf) {
+  const int n_sub = cd.n_sub, n_t = cd.n_t, rs = cd.rs;
+  const ST* zp = cd.z + (size_t)p * n_sub * n_t;
+  for (int k = tid_x(); k < n_sub * n_t; k += 64 * NW) {
+    const int s = k / n_t;
+    buf[s * rs + (k - s * n_t)] = zp[k];
+  }
+}
+// The copy a cube's rows allow (the batch passes it per cube): global-to-LDS
+// loads of 16 or 4 bytes per lane, else ordinary loads (16-bit samples in rows
+// of an odd length).
+template <int NW>
+__device__ __forceinline__ void stage_rows_w(const CubeDesc& cd, int p, ST* buf, int wv, int l) {
+  if (cd.dma_w == 16) stage_rows_async<NW, 16>(cd, p, buf, wv, l);
+  else if (cd.dma_w == 4) stage_rows_async<NW, 4>(cd, p, buf, wv, l);
+  else stage_rows_sync<NW>(cd, p, buf);
 }
 
 // Between requesting a pixel's rows and waiting for them, a wave issues no
@@ -390,7 +426,7 @@ __device__ __forceinline__ void stage_rows_async(const CubeDesc& cd, int p, ST* 
 // would wait for the row requests too.
 // ---------------------------------------------------------------------------
 // Persistent form of search_group for one pixel per workgroup: the workgroup
-// walks pixels blockIdx.x, blockIdx.x + gridDim.x, ...; its NW waves split the
+// walks pixels b, b + G, ... (workgroup b of G); its NW waves split the
 // DM trials round-robin as in search_group. When the layout allows, the rows of
 // the next pixel are requested with global-to-LDS loads as soon as no wave will
 // read the current rows again (after the last round's de-dispersion; with two
@@ -399,71 +435,187 @@ __device__ __forceinline__ void stage_rows_async(const CubeDesc& cd, int p, ST* 
 // normalisers are read once, so no vector-memory load is issued while row
 // requests are in flight (one counter tracks them all).
 // ---------------------------------------------------------------------------
+// A load through the scalar cache (the constant address space): for values the
+// kernel never writes, at uniform addresses.
+template <typename T>
+__device__ __forceinline__ T ld_const(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)(p);
+}
+
+// -inf in samples n_t .. rs-1 of every row of a tile.
+template <int NW>
+__device__ __forceinline__ void fill_tails(ST* buf, int n_sub, int n_t, int rs) {
+  const ST neg = from_f32<ST>(kNegInf);
+  const int tail = rs - n_t;
+  for (int k = tid_x(); k < n_sub * tail; k += 64 * NW) {
+    const int r = k / tail;
+    buf[r * rs + n_t + (k - r * tail)] = neg;
+  }
+}
+
+// The DM trials of one pixel whose rows are in zl; `release` runs once every
+// wave has read the rows for the last time (after the last round's
+// de-dispersion; it is called by every wave, and must contain the barrier
+// itself). The loop has no branches (a branch around the boxcar chain costs it
+// registers): waves past the last trial repeat it (writing the same values
+// twice), and a trial with no valid sample is searched with zero delays (its
+// row of `delays` holds zeros) and then reported as -inf / -1.
+template <int C, int NW, class Release>
+__device__ __forceinline__ void search_pixel_dms(const CubeDesc& cd, const int* delays, const int* dmaxv,
+                                                 const ST* zl, Reporter& rep, int wv, int l, Release&& release) {
+  const int n_dm = cd.n_dm, n_t = cd.n_t, n_sub = cd.n_sub, rs = cd.rs;
+  const int n_rounds = (n_dm + NW - 1) / NW;
+  for (int rd = 0; rd < n_rounds; ++rd) {
+    const int d = min(rd * NW + wv, n_dm - 1);
+    const int* dd = delays + (size_t)d * n_sub;
+    for (int pass = 0; pass < NSFRB_NPASS; ++pass) {
+      float cur[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) cur[c] = 0.f;
+      for (int s = 0; s < n_sub; ++s) add_row<C>(cur, zl + s * rs, ld_const(dd + s), l);
+      if (pass == NSFRB_NPASS - 1 && rd == n_rounds - 1) release();
+      nsfrb_chain<C>(pass, cur, rep);
+    }
+    // (read after the chain: a scalar held across it would push the chain's
+    // ballot masks out of scalar registers)
+    const bool searched = ld_const(dmaxv + d) < n_t;
+    rep.d = d;
+    rep.snr_lane = searched ? rep.snr_lane : kNegInf;
+    rep.toa_lane = searched ? rep.toa_lane : -1;
+    rep.flush();
+  }
+}
+
+// The per-pixel best (S/N, d, w, t) over the workgroup's waves; ends with a barrier.
+template <int NW>
+__device__ __forceinline__ void write_best(const CubeDesc& cd, int p, const Best& mine, Best* red, int wv, int l) {
+  if (l == 0) red[wv] = mine;
+  __syncthreads();
+  if (tid_x() == 0) {
+    Best b = red[0];
+    for (int w = 1; w < NW; ++w)
+      if (better(red[w].s, red[w].d, red[w].w, b)) b = red[w];
+    const bool ok = b.s > kNegInf;
+    cd.best_s[p] = ok ? b.s : kNegInf;
+    cd.best_d[p] = ok ? b.d : -1;
+    cd.best_w[p] = ok ? b.w : -1;
+    cd.best_t[p] = ok ? b.t : -1;
+  }
+}
+
+// Lane iw's S/N normaliser of a cube, through the scalar cache (no vector load).
+__device__ __forceinline__ float lane_norm(const CubeDesc& cd, int l) {
+  float v = 1.f;
+#pragma unroll
+  for (int iw = 0; iw < NSFRB_NW; ++iw) v = (l == iw) ? ld_const(cd.norms + iw) : v;
+  return v;
+}
+
+// Items [first, end) with a stride, each XCD taking a contiguous range of the
+// total when the grid is a multiple of 8 (workgroup b runs on XCD b mod 8):
+// neighbouring pixels' map entries (one 128-byte line holds 32 of them) are
+// then written by one XCD and leave its L2 as whole lines; with the plain
+// stride every line would be written back once per XCD.
+struct ItemRange {
+  long long first, end, stride;
+};
+template <int NW>
+__device__ __forceinline__ ItemRange xcd_items(long long n) {
+  const int g = n_wg<64 * NW>(), b = wg_id();
+  if ((g & 7) == 0) {
+    const long long x = b & 7;
+    return ItemRange{((n * x) >> 3) + (b >> 3), (n * (x + 1)) >> 3, (long long)(g >> 3)};
+  }
+  return ItemRange{(long long)b, n, (long long)g};
+}
+
+// Persistent single-cube form: one pixel per workgroup at a time; the next
+// pixel's rows (global-to-LDS, 16-byte lanes) are requested as soon as no
+// wave reads the current ones (after the last round's de-dispersion; with two
+// LDS buffers, at the start of the pixel). No vector-memory load is issued
+// while row requests are in flight (one counter tracks them all): delays and
+// DM bounds come through the scalar cache, the S/N normalisers are read once.
 template <int C, int NW, int NBUF>
 __device__ __forceinline__ void search_persistent(const CubeDesc& cd, const int* __restrict__ delays,
                                                   const int* __restrict__ dmaxv) {
   extern __shared__ unsigned char lds_raw[];
   __shared__ Best red[NW];
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int wv = __builtin_amdgcn_readfirstlane(tid_x() / kWave);
   const int l = lane_id();
-  const int rs = cd.rs, n_sub = cd.n_sub, n_t = cd.n_t, n_pix = cd.n_pix, n_dm = cd.n_dm;
-  const int tile = n_sub * rs;
+  const int tile = cd.n_sub * cd.rs;
   ST* bufs = reinterpret_cast<ST*>(lds_raw);
-  const ST neg = from_f32<ST>(kNegInf);
-  for (int i = threadIdx.x; i < NBUF * n_sub * (rs - n_t); i += 64 * NW) {
-    const int r = i / (rs - n_t);
-    bufs[r * rs + n_t + (i - r * (rs - n_t))] = neg;
-  }
-  const float norm_l = l < NSFRB_NW ? cd.norms[l] : 1.f;
-  const int n_rounds = (n_dm + NW - 1) / NW;
-  const int p_first = blockIdx.x;
-  if (p_first < n_pix) stage_rows_async<NW>(cd, p_first, bufs, wv, l);
+  for (int b = 0; b < NBUF; ++b) fill_tails<NW>(bufs + b * tile, cd.n_sub, cd.n_t, cd.rs);
+  const float norm_l = lane_norm(cd, l);
+  const ItemRange r = xcd_items<NW>(cd.n_pix);
+  if (r.first < r.end) stage_rows_async<NW>(cd, (int)r.first, bufs, wv, l);
   int it = 0;
-  for (int p = p_first; p < n_pix; p += gridDim.x, ++it) {
+  for (long long i = r.first; i < r.end; i += r.stride, ++it) {
+    const int p = (int)i;
+    const long long i_next = i + r.stride;
     ST* zl = bufs + (NBUF == 2 ? (it & 1) * tile : 0);
-    const int p_next = p + (int)gridDim.x;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (NBUF == 2 && p_next < n_pix) stage_rows_async<NW>(cd, p_next, bufs + ((it + 1) & 1) * tile, wv, l);
-    Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, n_pix}, p, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0, norm_l};
-    // The DM loop has no branches (a branch around the boxcar chain costs it
-    // registers): waves past the last trial repeat it (writing the same values
-    // twice), and a trial with no valid sample is searched with zero delays
-    // (row `delays` holds zeros for it) and then reported as -inf / -1.
-    for (int rd = 0; rd < n_rounds; ++rd) {
-      const int d = min(rd * NW + wv, n_dm - 1);
-      const int* dd = delays + (size_t)d * n_sub;
-      for (int pass = 0; pass < NSFRB_NPASS; ++pass) {
-        float cur[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) cur[c] = 0.f;
-        for (int s = 0; s < n_sub; ++s) add_row<C>(cur, zl + s * rs, dd[s], l);
-        if (NBUF == 1 && pass == NSFRB_NPASS - 1 && rd == n_rounds - 1) {
-          __syncthreads();   // no wave reads the rows of p again
-          if (p_next < n_pix) stage_rows_async<NW>(cd, p_next, bufs, wv, l);
-        }
-        nsfrb_chain<C>(pass, cur, rep);
+    if (NBUF == 2 && i_next < r.end) stage_rows_async<NW>(cd, (int)i_next, bufs + ((it + 1) & 1) * tile, wv, l);
+    Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, p, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0, norm_l};
+    search_pixel_dms<C, NW>(cd, delays, dmaxv, zl, rep, wv, l, [&]() {
+      if (NBUF == 1) {
+        __syncthreads();   // no wave reads the rows of p again
+        if (i_next < r.end) stage_rows_async<NW>(cd, (int)i_next, bufs, wv, l);
       }
-      // (read after the chain: a scalar held across it would push the chain's
-      // ballot masks out of scalar registers)
-      const bool searched = dmaxv[d] < n_t;
-      rep.d = d;
-      rep.snr_lane = searched ? rep.snr_lane : kNegInf;
-      rep.toa_lane = searched ? rep.toa_lane : -1;
-      rep.flush();
-    }
-    if (l == 0) red[wv] = rep.best;
+    });
+    write_best<NW>(cd, p, rep.best, red, wv, l);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
+// Persistent batch: the work items (one pixel each) of the cubes of one kernel
+// class, concatenated in cube order (descs[c].item_begin), walked as in
+// search_persistent. A workgroup's items increase, so its cube index only moves
+// forward; descriptors, delays and normalisers come through the scalar cache.
+// Cubes differ in n_sub, n_t, row pitch (rs) and delays: the -inf tails are
+// written for each item, and each cube's rows are copied with the widest lane
+// copy its alignment allows (dma_w). buf_stride: elements between the two LDS
+// buffers (the class's largest tile).
+template <int C, int NW, int NBUF>
+__device__ __forceinline__ void search_batch_persistent(const CubeDesc* __restrict__ descs, int n_cubes,
+                                                        long long n_items, int buf_stride) {
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ Best red[NW];
+  const int wv = __builtin_amdgcn_readfirstlane(tid_x() / kWave);
+  const int l = lane_id();
+  ST* bufs = reinterpret_cast<ST*>(lds_raw);
+  auto cube_of = [&](long long i, int c) {
+    while (c + 1 < n_cubes && i >= ld_const(&descs[c + 1].item_begin)) ++c;
+    return c;
+  };
+  auto stage = [&](int c, long long i, ST* buf) {
+    const CubeDesc cd = ld_const(descs + c);
+    fill_tails<NW>(buf, cd.n_sub, cd.n_t, cd.rs);
+    stage_rows_w<NW>(cd, (int)(i - cd.item_begin), buf, wv, l);
+  };
+  const ItemRange r = xcd_items<NW>(n_items);
+  int c = r.first < r.end ? cube_of(r.first, 0) : 0;
+  if (r.first < r.end) stage(c, r.first, bufs);
+  int it = 0;
+  for (long long i = r.first; i < r.end; i += r.stride, ++it) {
+    const CubeDesc cd = ld_const(descs + c);
+    const int p = (int)(i - cd.item_begin);
+    const long long i_next = i + r.stride;
+    const int c_next = i_next < r.end ? cube_of(i_next, c) : c;
+    ST* zl = bufs + (NBUF == 2 ? (it & 1) * buf_stride : 0);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) {
-      Best b = red[0];
-      for (int w = 1; w < NW; ++w)
-        if (better(red[w].s, red[w].d, red[w].w, b)) b = red[w];
-      const bool ok = b.s > kNegInf;
-      cd.best_s[p] = ok ? b.s : kNegInf;
-      cd.best_d[p] = ok ? b.d : -1;
-      cd.best_w[p] = ok ? b.w : -1;
-      cd.best_t[p] = ok ? b.t : -1;
-    }
+    if (NBUF == 2 && i_next < r.end) stage(c_next, i_next, bufs + ((it + 1) & 1) * buf_stride);
+    Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, p, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0,
+                 lane_norm(cd, l)};
+    search_pixel_dms<C, NW>(cd, cd.delays, cd.dmax, zl, rep, wv, l, [&]() {
+      if (NBUF == 1) {
+        __syncthreads();   // no wave reads the rows of this item again
+        if (i_next < r.end) stage(c_next, i_next, bufs);
+      }
+    });
+    write_best<NW>(cd, p, rep.best, red, wv, l);
+    c = c_next;
   }
   __builtin_amdgcn_s_waitcnt(0);
 }
@@ -479,20 +631,10 @@ __device__ __forceinline__ void search_cube(const nsfrb::CubeDesc& cd) {
   __shared__ Best red[NW];
   ST* zl = reinterpret_cast<ST*>(lds_raw);
   const int n_items = (cd.n_pix + PIX - 1) / PIX;
-  for (int blk = blockIdx.x; blk < n_items; blk += gridDim.x) {
+  const int g = n_wg<64 * NW>();
+  for (int blk = wg_id(); blk < n_items; blk += g) {
     int item = blk;
-    if ((n_items & 7) == 0 && (int)gridDim.x == n_items) item = (blk & 7) * (n_items >> 3) + (blk >> 3);
+    if ((n_items & 7) == 0 && g == n_items) item = (blk & 7) * (n_items >> 3) + (blk >> 3);
     search_group<C, PIX, NW>(cd, item * PIX, zl, red);
   }
-}
-
-// Persistent batch: every workgroup strides over the concatenated work items of
-// all cubes; each item dispatches to the body compiled for its cube's class.
-__device__ __forceinline__ int find_cube(const nsfrb::CubeDesc* descs, int n_cubes, long long item) {
-  int lo = 0, hi = n_cubes - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].item_begin <= item) lo = mid; else hi = mid - 1;
-  }
-  return lo;
 }

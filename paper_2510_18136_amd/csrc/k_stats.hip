@@ -486,24 +486,17 @@ __device__ __forceinline__ double div_markstein(double a, double b, double r) {
 
 // Statistics + normalisation of one series held in LDS (sample t at xs[t];
 // NaN from n_t up to 64 V), read as x(j) <-> t = 64 j + lane.
+// xmin, xmax: this lane's partial extremes of the series (NaN padding is
+// ignored by fminf/fmaxf), any_bad: whether the series holds a non-finite
+// sample; both come from the load, which sees every sample once.
 template <int V, typename ST>
 __device__ __forceinline__ void process_series(const float* xs, int p, int s, int n_t, int n_sub, int mode,
                                                const double* __restrict__ med_in, const double* __restrict__ sig_in,
                                                double* __restrict__ med_out, double* __restrict__ sig_out,
                                                ST* __restrict__ z, unsigned long long* __restrict__ flag_count,
-                                               const SeriesCtx& cx) {
+                                               const SeriesCtx& cx, float xmin, float xmax, bool any_bad) {
   const int l = lane_id();
   const LdsSeries x{xs, l};
-  bool bad = false;
-  float xmin = __builtin_inff(), xmax = -__builtin_inff();   // NaN padding is ignored by fminf/fmaxf
-#pragma unroll
-  for (int j = 0; j < V; ++j) {
-    const float v = x(j);
-    if (64 * j + l < n_t && !__builtin_isfinite(v)) bad = true;
-    xmin = fminf(xmin, v);
-    xmax = fmaxf(xmax, v);
-  }
-  const bool any_bad = ballot(bad) != 0;
 
   long long nflag = 0;
   double med = 0.0, sig = 1.0;
@@ -637,14 +630,34 @@ __attribute__((amdgpu_waves_per_eu(StatShape<V>::kMinWavesPerEU))) void k_stats_
     const float v = to_f32(src[(size_t)(ok ? tr : 0) * plane]);
     stage[q] = ok ? v : __builtin_nanf("");
   }
+  // the thread's samples all belong to series c_ld: its partial extremes and
+  // non-finite flag go to that series' (not yet used) histogram slots, where
+  // the series' wave combines the kRowStep partials (saves a pass over the row)
+  float tmin = __builtin_inff(), tmax = -__builtin_inff();
+  bool tbad = false;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int t = q * kRowStep + r0;
+    tbad |= (t < n_t) && !__builtin_isfinite(stage[q]);
+    tmin = fminf(tmin, stage[q]);
+    tmax = fmaxf(tmax, stage[q]);
+  }
   float* my_row = series + c_ld * RS + r0;
 #pragma unroll
   for (int q = 0; q < kPer; ++q) my_row[q * kRowStep] = stage[q];
+  uint32_t* part = hist_all[c_ld];
+  part[r0] = __float_as_uint(tmin);
+  part[kRowStep + r0] = __float_as_uint(tmax);
+  part[2 * kRowStep + r0] = tbad ? 1u : 0u;
   __syncthreads();
   SeriesCtx cx{hist_all[w], list_all[w], n_t};
+  const int l = lane_id();
+  const float pmin = __uint_as_float(cx.hist[l]), pmax = __uint_as_float(cx.hist[kRowStep + l]);
+  const bool any_bad = ballot(cx.hist[2 * kRowStep + l] != 0u) != 0;
+  wave_lds_sync();                                 // the histogram slots are reused from here on
   if (p0 + w < n_pix)
     process_series<V, ST>(series + w * RS, p0 + w, s, n_t, n_sub, mode, med_in, sig_in, med_out, sig_out, z,
-                          flag_count, cx);
+                          flag_count, cx, pmin, pmax, any_bad);
 }
 
 // ------------------------------------------------------------ launcher

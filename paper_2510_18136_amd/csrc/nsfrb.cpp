@@ -296,12 +296,13 @@ static const char* store_type_name(int store) {
   return store == DT_F32 ? "float" : (store == DT_F16 ? "_Float16" : "nsfrb::bf16_t");
 }
 
-// Translation unit with single-cube kernels for (C, PIX) pairs and, if
-// `batch` is set, the persistent batch kernel dispatching over `classes`.
 // A persistent kernel to instantiate: samples per lane, waves, LDS buffers.
 struct PersistentKernel {
   int C, NW, n_buf;
 };
+// Translation unit with the per-DM kernels of `single` (C, PIX, NW), the
+// persistent single-cube kernels, and one persistent batch kernel per entry of
+// `batch` (C, LDS buffers in PIX, NW).
 static std::string gen_source(int store, int nw, int npass, const std::string& chain,
                               const std::vector<KernelClass>& single, const std::vector<KernelClass>& batch,
                               const std::vector<PersistentKernel>& persistent = {}) {
@@ -318,30 +319,13 @@ static std::string gen_source(int store, int nw, int npass, const std::string& c
   for (const auto& k : persistent)
     o << "extern \"C\" __global__ __launch_bounds__(" << 64 * k.NW << ") void nsfrb_persistent_c" << k.C << "_w"
       << k.NW << "_b" << k.n_buf << "(nsfrb::CubeDesc cd, const int* __restrict__ delays, const int* __restrict__ dmax"
-      << ") { search_persistent<" << k.C << ", " << k.NW << ", " << k.n_buf << ">(cd, delays, dmax); }\n";
-  // one persistent kernel per class of the batch: its workgroups take the work
-  // items of that class's cubes (descriptors contiguous, item_begin relative)
-  // from a device counter, one item at a time, until the counter passes n_items
+      << ") { nsfrb::search_persistent<" << k.C << ", " << k.NW << ", " << k.n_buf << ">(cd, delays, dmax); }\n";
+  // one persistent kernel per class of the batch (PIX carries its LDS buffers)
   for (size_t i = 0; i < batch.size(); ++i)
     o << "extern \"C\" __global__ __launch_bounds__(" << 64 * batch[i].NW << ") void nsfrb_batch_kernel_" << i
-      << "(const nsfrb::CubeDesc* __restrict__ descs, int n_cubes, long long n_items,"
-         " unsigned long long* __restrict__ next_item) {\n"
-         "  using namespace nsfrb;\n"
-         "  extern __shared__ unsigned char lds_raw[];\n"
-         "  __shared__ Best red[" << batch[i].NW << "];\n"
-         "  __shared__ long long item;\n"
-         "  ST* zl = reinterpret_cast<ST*>(lds_raw);\n"
-         "  for (;;) {\n"
-         "    if (threadIdx.x == 0) item = (long long)atomicAdd(next_item, 1ull);\n"
-         "    __syncthreads();\n"
-         "    const long long it = item;\n"
-         "    __syncthreads();\n"
-         "    if (it >= n_items) break;\n"
-         "    const CubeDesc cd = descs[find_cube(descs, n_cubes, it)];\n"
-         "    search_group<" << batch[i].C << ", " << batch[i].PIX << ", " << batch[i].NW
-      << ">(cd, (int)(it - cd.item_begin) * "
-      << batch[i].PIX << ", zl, red);\n"
-         "  }\n}\n";
+      << "(const nsfrb::CubeDesc* __restrict__ descs, int n_cubes, long long n_items, int buf_stride) {\n"
+         "  nsfrb::search_batch_persistent<" << batch[i].C << ", " << batch[i].NW << ", " << batch[i].PIX
+      << ">(descs, n_cubes, n_items, buf_stride);\n}\n";
   return o.str();
 }
 
@@ -496,10 +480,13 @@ extern "C" int nsfrb_debug_plan_source(const nsfrb_search_config* cfg, char* out
   if (gen_chain(std::vector<int>(cfg->width, cfg->width + cfg->n_width), chain, &npass, max_acc) != NSFRB_OK)
     return -1;
   std::vector<PersistentKernel> pks;
+  std::vector<KernelClass> bks;          // batch kernels of the same shapes (PIX carries the LDS buffers)
   for (const PersistentPlan& pp : persistent_candidates(cfg->n_dm, cfg->n_sub, cfg->n_time, C, dmax_search,
-                                                        cfg->store_dtype))
+                                                        cfg->store_dtype)) {
     pks.push_back({C, pp.NW, pp.n_buf});
-  const std::string src = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, ks, pks);
+    bks.push_back({C, pp.n_buf, pp.NW});
+  }
+  const std::string src = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, bks, pks);
   if (out && cap > 0) std::snprintf(out, (size_t)cap, "%s", src.c_str());
   if (compile) {
     std::vector<char> code;
@@ -739,7 +726,7 @@ static CubeDescHost cube_desc(const nsfrb_search* h, const void* z, int n_pix) {
   d.n_t = c.n_time;
   d.n_dm = c.n_dm;
   d.rs = h->rs;
-  d.cls = 0;
+  d.dma_w = 0;
   d.item_begin = 0;
   return d;
 }
@@ -1079,8 +1066,12 @@ extern "C" nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* i
 
 // ------------------------------------------------------------------- batch
 // One kernel class of a batch: the cubes whose tuned plan has this (C, PIX).
+// One kernel class of a batch: the cubes with the same samples per lane (C) and
+// waves per workgroup; one persistent kernel walks all their pixels.
 struct BatchClass {
-  KernelClass k;
+  KernelClass k;                         // C, PIX = 1, NW
+  int n_buf = 1;                         // LDS pixel buffers
+  int buf_stride = 0;                    // elements between the buffers (the class's largest tile)
   hipFunction_t fn = nullptr;
   int first_desc = 0, n_cubes = 0;       // descriptors [first_desc, first_desc + n_cubes)
   long long n_items = 0;
@@ -1095,7 +1086,6 @@ struct nsfrb_batch {
   std::vector<CubeDescHost> descs;        // grouped by class; item_begin relative to the class
   std::vector<int> desc_of_cube;          // cube index -> descriptor index
   CubeDescHost* d_descs = nullptr;
-  unsigned long long* d_next = nullptr;   // per-class work counters, cleared by a fill kernel each run
   long long n_items = 0;
   hipModule_t mod = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -1114,7 +1104,6 @@ static void batch_release(nsfrb_batch* b) {
   if (b->graph) hipGraphDestroy(b->graph);
   if (b->cap_stream) hipStreamDestroy(b->cap_stream);
   if (b->d_descs) hipFree(b->d_descs);
-  if (b->d_next) hipFree(b->d_next);
   if (b->done) hipEventDestroy(b->done);
   for (auto* h : b->cubes) release(h);
   delete b;
@@ -1146,17 +1135,21 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
     if (st != NSFRB_OK) return fail(st, "cube " + std::to_string(i) + ": " + g_last_error);
     b->cubes.push_back(h);
   }
-  // kernel classes: distinct (samples per lane, pixels per workgroup) of the cubes' tuned plans
+  // kernel classes: cubes with the same samples per lane; 16 waves when there
+  // are at least 16 DM trials (the trials are shared by all cubes), else 8
+  const int nw_b = c0.n_dm >= 16 ? 16 : 8;
+  const size_t sz = dtype_size(c0.store_dtype);
+  const int align = c0.store_dtype == DT_F32 ? 4 : 8;          // row pitch: whole 16-byte vectors
   std::vector<int> cls_of(b->cubes.size());
   for (size_t i = 0; i < b->cubes.size(); ++i) {
     nsfrb_search* h = b->cubes[i];
     int cls = -1;
     for (size_t k = 0; k < b->classes.size(); ++k)
-      if (b->classes[k].k.C == h->C && b->classes[k].k.PIX == h->pix && b->classes[k].k.NW == h->nw) cls = (int)k;
+      if (b->classes[k].k.C == h->C) cls = (int)k;
     if (cls < 0) {
       cls = (int)b->classes.size();
       b->classes.emplace_back();
-      b->classes.back().k = {h->C, h->pix, h->nw};
+      b->classes.back().k = {h->C, 1, nw_b};
     }
     cls_of[i] = cls;
   }
@@ -1168,14 +1161,20 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
       if (cls_of[i] != (int)c) continue;
       nsfrb_search* h = b->cubes[i];
       CubeDescHost d = cube_desc(h, nullptr, h->n_pix);
-      d.cls = (int)c;
+      d.rs = (h->rs + align - 1) / align * align;
+      d.delays = h->d_delays_zeroed;
       d.item_begin = bc.n_items;
-      bc.n_items += (h->n_pix + h->pix - 1) / h->pix;
+      bc.n_items += h->n_pix;
       b->desc_of_cube[i] = (int)b->descs.size();
       b->descs.push_back(d);
-      bc.lds = std::max(bc.lds, lds_bytes_for(h->pix, h->cfg.n_sub, h->rs, h->cfg.store_dtype));
+      bc.buf_stride = std::max(bc.buf_stride, h->cfg.n_sub * d.rs);
     }
     bc.n_cubes = (int)b->descs.size() - bc.first_desc;
+    const size_t tile = (size_t)bc.buf_stride * sz;
+    if (tile > kLdsBudget)
+      return fail(NSFRB_ERR_UNSUPPORTED, "a batch cube's rows do not fit in LDS with 16-byte row pitches");
+    bc.n_buf = 2 * tile <= kLdsBudget ? 2 : 1;
+    bc.lds = bc.n_buf * tile;
     b->n_items += bc.n_items;
   }
   std::string chain;
@@ -1186,7 +1185,7 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
   if (st != NSFRB_OK) return st;
   HIP_TRY(hipSetDevice(b->device));
   std::vector<KernelClass> ks;
-  for (const auto& bc : b->classes) ks.push_back(bc.k);
+  for (const auto& bc : b->classes) ks.push_back({bc.k.C, bc.n_buf, bc.k.NW});   // PIX carries the buffers
   st = load_module(b->device, gen_source(b->store, b->nw, npass, chain, {}, ks), &b->mod);
   if (st != NSFRB_OK) return st;
   int n_cu = 0;
@@ -1206,7 +1205,6 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
     bc.grid = (unsigned)std::max(1LL, std::min(g, bc.n_items));
   }
   HIP_TRY(dalloc(&b->d_descs, b->descs.size()));
-  HIP_TRY(dalloc(&b->d_next, b->classes.size()));
   HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
   *out = b.release();
@@ -1269,9 +1267,8 @@ static nsfrb_status batch_enqueue(nsfrb_batch* b, const void* const* d_cubes, hi
     const CubeDescHost* descs = b->d_descs + bc.first_desc;
     int n = bc.n_cubes;
     long long items = bc.n_items;
-    unsigned long long* next = b->d_next + c;
-    HIP_TRY(launch_zero_u64(next, st));
-    void* args[] = {(void*)&descs, &n, &items, (void*)&next};
+    int stride = bc.buf_stride;
+    void* args[] = {(void*)&descs, &n, &items, &stride};
     HIP_TRY(hipModuleLaunchKernel(bc.fn, bc.grid, 1, 1, 64 * bc.k.NW, 1, 1, (unsigned)bc.lds, st, args, nullptr));
   }
   return batch_candidates(b, st);
@@ -1290,7 +1287,14 @@ extern "C" nsfrb_status nsfrb_batch_run(nsfrb_batch* b, const void* const* d_cub
     if (b->ran) HIP_TRY(hipEventSynchronize(b->done));
     for (size_t i = 0; i < b->cubes.size(); ++i) {
       nsfrb_search* h = b->cubes[i];
-      b->descs[b->desc_of_cube[i]].z = h->cfg.layout == NSFRB_LAYOUT_TSP ? h->d_z : d_cubes[i];
+      CubeDescHost& d = b->descs[b->desc_of_cube[i]];
+      d.z = h->cfg.layout == NSFRB_LAYOUT_TSP ? h->d_z : d_cubes[i];
+      // row copy the cube allows: global-to-LDS loads of 16 (4) bytes per lane
+      // for rows of whole 16-byte (4-byte) vectors from a 16-byte (4-byte)
+      // aligned cube, else ordinary loads (2)
+      const size_t row_bytes = (size_t)h->cfg.n_time * dtype_size(h->cfg.store_dtype);
+      const uintptr_t zp = reinterpret_cast<uintptr_t>(d.z);
+      d.dma_w = (row_bytes % 16 == 0 && zp % 16 == 0) ? 16 : (row_bytes % 4 == 0 && zp % 4 == 0) ? 4 : 2;
     }
     HIP_TRY(hipMemcpy(b->d_descs, b->descs.data(), b->descs.size() * sizeof(CubeDescHost), hipMemcpyHostToDevice));
     b->desc_ptrs = ptrs;

@@ -52,7 +52,8 @@ struct CubeDescHost {
   int* best_d;
   int* best_w;
   int* best_t;
-  int n_pix, n_sub, n_t, n_dm, rs, cls;
+  int n_pix, n_sub, n_t, n_dm, rs;
+  int dma_w;          // batch row copy: global-to-LDS bytes per lane (16 or 4), else ordinary loads
   long long item_begin;
 };
 static_assert(sizeof(CubeDescHost) == 112, "CubeDesc layout");

@@ -5,6 +5,8 @@
 * on small host-generated cubes the batch matches the FP64 oracle;
 * at the benchmarked size (64 uneven cubes, ~108 GB) graph replay equals plain
   launches bit for bit, and the smallest cube matches the oracle in full;
+* every row copy of the batch kernel (16- and 4-byte global-to-LDS loads,
+  ordinary loads for odd 16-bit rows and misaligned cubes) equals plain launches;
 * the device Philox4x32-10 words equal the host implementation bit for bit,
   and its Box-Muller normals agree with an FP64 evaluation.
 """
@@ -140,6 +142,54 @@ def test_batch_matches_oracle_on_small_cubes():
             clear = fin & (o["margin"] > 2e-4)
             assert np.array_equal(toa[clear], o["toa"][clear])
             assert ntot == o["n_total"]
+
+
+def test_batch_row_copies_of_every_alignment():
+    """The persistent batch copies a cube's rows into LDS with 16-byte or 4-byte
+    global-to-LDS loads, or with ordinary loads (16-bit rows of odd length, or a
+    cube that starts off a 4-byte boundary): every path gives maps and
+    candidates bitwise equal to one plain launch per cube, and the odd cube
+    matches the oracle."""
+    widths = [1, 2, 4, 8, 16]
+    cases = [(16, 8, 256, 0), (16, 8, 100, 0), (8, 16, 101, 0), (8, 8, 64, 1), (24, 16, 333, 0)]
+    stream = torch.cuda.current_stream().cuda_stream
+    cfgs, cubes, views = [], [], []
+    for k, (side, ns, nt, shift) in enumerate(cases):
+        c = nsfrb.SearchConfig(side, side, nt, np.linspace(1.311, 1.499, ns), C1_DMS, widths, in_dtype="f16",
+                               store_dtype="f16", norm="none", layout="pst", snr_threshold=5.0, max_candidates=16)
+        n = side * side * ns * nt
+        x = torch.empty(n + 8, dtype=torch.float16, device="cuda")
+        v = x[shift:shift + n]                       # shift 1: a cube 2 bytes past an aligned address
+        nsfrb.generate_noise(v.data_ptr(), "f16", "pst", side * side, ns, nt, 700 + k, stream=stream)
+        off = delay_table(c.freqs, c.freqs.max(), 134.2, [500.0])[0]
+        nsfrb.inject_boxcar(v.data_ptr(), "f16", "pst", side * side, ns, nt, pixel=side * side // 2, t0=20,
+                            width=4, amp=2.0, offsets=off, stream=stream)
+        cfgs.append(c)
+        cubes.append(x)
+        views.append(v)
+    ptrs = [v.data_ptr() for v in views]
+    assert ptrs[3] % 4 == 2
+    print(f"[gpu] batch row copies: {len(cfgs)} cubes", flush=True)
+    with nsfrb.Batch(cfgs) as b:
+        b.run_separate(ptrs, stream)
+        ref = results(b, len(cfgs))
+        b.use_graph(False)
+        b.run(ptrs, stream)
+        same(results(b, len(cfgs)), ref)
+        b.use_graph(True)
+        b.run(ptrs, stream)
+        same(results(b, len(cfgs)), ref)
+    k = 2
+    c = cfgs[k]
+    z = views[k].cpu().numpy().astype(np.float32).reshape(c.n_pix, c.n_sub, c.n_time)
+    o = oracle_run(np.transpose(z, (2, 1, 0)).copy(), c)
+    snr, toa, cands, ntot = ref[k]
+    fin = np.isfinite(o["snr_max"])
+    assert np.array_equal(np.isfinite(snr), fin)
+    assert np.abs(snr[fin] - o["snr_max"][fin]).max() <= 2e-4
+    clear = fin & (o["margin"] > 2e-4)
+    np.testing.assert_array_equal(toa[clear], o["toa"][clear])
+    assert ntot == o["n_total"]
 
 
 def test_injectors_match_their_definition():
