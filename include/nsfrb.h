@@ -55,9 +55,12 @@ typedef enum {
                            requires NSFRB_NORM_NONE and in_dtype == store_dtype; searched in place */
 } nsfrb_layout;
 
+/* Normalisation (section 2.2: the median of each pixel's series is subtracted
+ * and the series is scaled by its noise). The series is a (pixel, sub-band)
+ * series; one set of statistics per pixel over all sub-bands is not offered
+ * (value 1 is not used and is refused as unknown). */
 typedef enum {
   NSFRB_NORM_PIXEL_SUBBAND = 0, /* median/MAD per (pixel, sub-band) over time        */
-  NSFRB_NORM_PIXEL = 1,         /* median/MAD per pixel over (time, sub-band)        */
   NSFRB_NORM_EXTERNAL = 2,      /* caller supplies median and sigma per (p, s)       */
   NSFRB_NORM_NONE = 3           /* z = x (cast to the store dtype)                   */
 } nsfrb_norm;

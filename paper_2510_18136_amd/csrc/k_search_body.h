@@ -152,7 +152,7 @@ __device__ __forceinline__ bool better(float s, int d, int w, const Best& b) {
 // lane maxima by a max3 tree over groups of three registers, the wave maximum
 // by DPP, the first lane L holding it by a ballot, then the first register of
 // lane L holding it from one ballot per register (compares write lane masks
-// to scalar registers; the lane's bit is tested on the scalar unit).
+// to scalar registers; lane L's bit is tested on the scalar unit).
 template <int C>
 __device__ __forceinline__ void max_first(const float (&b)[C], float& M, int& T) {
   constexpr int G = (C + 2) / 3;
@@ -170,10 +170,15 @@ __device__ __forceinline__ void max_first(const float (&b)[C], float& M, int& T)
   M = wave_max_f(m);
   // some lane's maximum equals M, so the ballot is never empty
   const int L = __ffsll((long long)ballot(m == M)) - 1;
-  const uint64_t bitL = 1ull << L;
   int cf = C - 1;
 #pragma unroll
-  for (int c = C - 2; c >= 0; --c) cf = (ballot(b[c] == M) & bitL) ? c : cf;
+  for (int c = C - 2; c >= 0; --c) {
+    // cf = c if lane L's bit of the compare mask is set: s_bitcmp1_b64 tests
+    // the bit straight into SCC (two scalar instructions per register; the
+    // compiler's mask-and-compare form takes three)
+    const uint64_t mk = ballot(b[c] == M);
+    asm("s_bitcmp1_b64 %1, %2\n\ts_cselect_b32 %0, %3, %0" : "+s"(cf) : "s"(mk), "s"(L), "n"(c) : "scc");
+  }
   T = (M > kNegInf) ? C * L + cf : -1;
 }
 
@@ -511,22 +516,26 @@ __device__ __forceinline__ float lane_norm(const CubeDesc& cd, int l) {
   return v;
 }
 
-// Items [first, end) with a stride, each XCD taking a contiguous range of the
-// total when the grid is a multiple of 8 (workgroup b runs on XCD b mod 8):
-// neighbouring pixels' map entries (one 128-byte line holds 32 of them) are
-// then written by one XCD and leave its L2 as whole lines; with the plain
-// stride every line would be written back once per XCD.
-struct ItemRange {
-  long long first, end, stride;
+// The work items of one workgroup, in increasing order. When the grid is a
+// multiple of 8 (workgroup b runs on XCD b mod 8), items are cut into chunks of
+// 32 (one 128-byte line of a map row holds 32 pixels' entries), chunk j
+// belongs to XCD j mod 8, and the workgroups of an XCD take that XCD's items in
+// turn. Neighbouring pixels' map entries then leave one XCD's L2 as whole
+// lines (with a plain stride every line would be written back once per XCD),
+// and every XCD gets an equal share of each stretch of items, so cubes of
+// unequal cost in a batch do not load one XCD more than another.
+struct ItemWalk {
+  long long n;
+  int x, k0, step;           // XCD (-1: plain stride), first index, index step
+  __device__ __forceinline__ long long item(long long k) const {
+    return x < 0 ? k : ((((k >> 5) << 3) + x) << 5) + (k & 31);
+  }
 };
 template <int NW>
-__device__ __forceinline__ ItemRange xcd_items(long long n) {
+__device__ __forceinline__ ItemWalk xcd_walk(long long n) {
   const int g = n_wg<64 * NW>(), b = wg_id();
-  if ((g & 7) == 0) {
-    const long long x = b & 7;
-    return ItemRange{((n * x) >> 3) + (b >> 3), (n * (x + 1)) >> 3, (long long)(g >> 3)};
-  }
-  return ItemRange{(long long)b, n, (long long)g};
+  if ((g & 7) == 0) return ItemWalk{n, b & 7, b >> 3, g >> 3};
+  return ItemWalk{n, -1, b, g};
 }
 
 // Persistent single-cube form: one pixel per workgroup at a time; the next
@@ -546,24 +555,26 @@ __device__ __forceinline__ void search_persistent(const CubeDesc& cd, const int*
   ST* bufs = reinterpret_cast<ST*>(lds_raw);
   for (int b = 0; b < NBUF; ++b) fill_tails<NW>(bufs + b * tile, cd.n_sub, cd.n_t, cd.rs);
   const float norm_l = lane_norm(cd, l);
-  const ItemRange r = xcd_items<NW>(cd.n_pix);
-  if (r.first < r.end) stage_rows_async<NW>(cd, (int)r.first, bufs, wv, l);
-  int it = 0;
-  for (long long i = r.first; i < r.end; i += r.stride, ++it) {
+  const ItemWalk r = xcd_walk<NW>(cd.n_pix);
+  long long k = r.k0, i = r.item(k);
+  if (i < r.n) stage_rows_async<NW>(cd, (int)i, bufs, wv, l);
+  for (int it = 0; i < r.n; ++it) {
     const int p = (int)i;
-    const long long i_next = i + r.stride;
+    k += r.step;
+    const long long i_next = r.item(k);
     ST* zl = bufs + (NBUF == 2 ? (it & 1) * tile : 0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (NBUF == 2 && i_next < r.end) stage_rows_async<NW>(cd, (int)i_next, bufs + ((it + 1) & 1) * tile, wv, l);
+    if (NBUF == 2 && i_next < r.n) stage_rows_async<NW>(cd, (int)i_next, bufs + ((it + 1) & 1) * tile, wv, l);
     Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, p, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0, norm_l};
     search_pixel_dms<C, NW>(cd, delays, dmaxv, zl, rep, wv, l, [&]() {
       if (NBUF == 1) {
         __syncthreads();   // no wave reads the rows of p again
-        if (i_next < r.end) stage_rows_async<NW>(cd, (int)i_next, bufs, wv, l);
+        if (i_next < r.n) stage_rows_async<NW>(cd, (int)i_next, bufs, wv, l);
       }
     });
     write_best<NW>(cd, p, rep.best, red, wv, l);
+    i = i_next;
   }
   __builtin_amdgcn_s_waitcnt(0);
 }
@@ -593,29 +604,31 @@ __device__ __forceinline__ void search_batch_persistent(const CubeDesc* __restri
     fill_tails<NW>(buf, cd.n_sub, cd.n_t, cd.rs);
     stage_rows_w<NW>(cd, (int)(i - cd.item_begin), buf, wv, l);
   };
-  const ItemRange r = xcd_items<NW>(n_items);
-  int c = r.first < r.end ? cube_of(r.first, 0) : 0;
-  if (r.first < r.end) stage(c, r.first, bufs);
-  int it = 0;
-  for (long long i = r.first; i < r.end; i += r.stride, ++it) {
+  const ItemWalk r = xcd_walk<NW>(n_items);
+  long long k = r.k0, i = r.item(k);
+  int c = i < r.n ? cube_of(i, 0) : 0;
+  if (i < r.n) stage(c, i, bufs);
+  for (int it = 0; i < r.n; ++it) {
     const CubeDesc cd = ld_const(descs + c);
     const int p = (int)(i - cd.item_begin);
-    const long long i_next = i + r.stride;
-    const int c_next = i_next < r.end ? cube_of(i_next, c) : c;
+    k += r.step;
+    const long long i_next = r.item(k);
+    const int c_next = i_next < r.n ? cube_of(i_next, c) : c;
     ST* zl = bufs + (NBUF == 2 ? (it & 1) * buf_stride : 0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (NBUF == 2 && i_next < r.end) stage(c_next, i_next, bufs + ((it + 1) & 1) * buf_stride);
+    if (NBUF == 2 && i_next < r.n) stage(c_next, i_next, bufs + ((it + 1) & 1) * buf_stride);
     Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, p, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0,
                  lane_norm(cd, l)};
     search_pixel_dms<C, NW>(cd, cd.delays, cd.dmax, zl, rep, wv, l, [&]() {
       if (NBUF == 1) {
         __syncthreads();   // no wave reads the rows of this item again
-        if (i_next < r.end) stage(c_next, i_next, bufs);
+        if (i_next < r.n) stage(c_next, i_next, bufs);
       }
     });
     write_best<NW>(cd, p, rep.best, red, wv, l);
     c = c_next;
+    i = i_next;
   }
   __builtin_amdgcn_s_waitcnt(0);
 }

@@ -117,8 +117,8 @@ static nsfrb_status validate(const nsfrb_search_config* c) {
     else if (c->width[i] > kMaxTime) return fail(NSFRB_ERR_UNSUPPORTED, "widths above 4096");
   if (c->in_dtype < 0 || c->in_dtype > 2 || c->store_dtype < 0 || c->store_dtype > 2)
     return fail(NSFRB_ERR_INVALID_ARG, "unknown dtype");
-  if (c->norm < 0 || c->norm > 3) return fail(NSFRB_ERR_INVALID_ARG, "unknown normalisation mode");
-  if (c->norm == NSFRB_NORM_PIXEL) return fail(NSFRB_ERR_UNSUPPORTED, "NSFRB_NORM_PIXEL is not implemented");
+  if (c->norm != NSFRB_NORM_PIXEL_SUBBAND && c->norm != NSFRB_NORM_EXTERNAL && c->norm != NSFRB_NORM_NONE)
+    return fail(NSFRB_ERR_INVALID_ARG, "unknown normalisation mode");
   if (c->layout != NSFRB_LAYOUT_TSP && c->layout != NSFRB_LAYOUT_PST) return fail(NSFRB_ERR_INVALID_ARG, "unknown layout");
   if (c->layout == NSFRB_LAYOUT_PST && (c->norm != NSFRB_NORM_NONE || c->in_dtype != c->store_dtype))
     return fail(NSFRB_ERR_INVALID_ARG, "NSFRB_LAYOUT_PST needs NSFRB_NORM_NONE and in_dtype == store_dtype");
@@ -421,14 +421,25 @@ static std::vector<KernelClass> plan_candidates(int C, int n_dm, int n_sub, int 
 
 // ------------------------------------------------ persistent kernel plans
 // The persistent kernel keeps one pixel per workgroup of NW waves (DM trials
-// round-robin, as the per-DM kernel) and walks pixels blockIdx.x, +gridDim.x,
-// ...; the next pixel's rows are requested with global-to-LDS loads while the
+// round-robin, as the per-DM kernel) and walks its pixels (ItemWalk);
+// the next pixel's rows are requested with global-to-LDS loads while the
 // current one is searched. Rows are whole 16-byte vectors (n_t * store bytes a
-// multiple of 16, pitch padded to 16 bytes); two LDS buffers when they fit.
+// multiple of 16, pitch padded to 16 bytes), in one or two LDS buffers.
 struct PersistentPlan {
   int NW = 16, rs = 0, n_buf = 1;
   size_t lds = 0;
 };
+
+// LDS buffers for a persistent kernel of nw waves with a tile of `tile` bytes:
+// two (the next pixel's rows load during the whole current pixel) unless that
+// leaves fewer workgroups on a CU than one buffer does, counting at most the 16
+// waves per CU that a search kernel's register use allows; 0 if no tile fits.
+static int persistent_buffers(size_t tile, int nw) {
+  if (tile > kLdsBudget) return 0;
+  if (2 * tile > kLdsBudget) return 1;
+  auto wgs = [&](size_t nb) { return (int)((160 * 1024) / (nb * tile + 1024)); };
+  return wgs(2) >= std::min(wgs(1), std::max(1, 16 / nw)) ? 2 : 1;
+}
 
 static bool plan_persistent(int n_sub, int n_t, int C, int dmax_search, int store, int NW, PersistentPlan& out) {
   out = PersistentPlan{};
@@ -437,10 +448,9 @@ static bool plan_persistent(int n_sub, int n_t, int C, int dmax_search, int stor
   const int align = store == DT_F32 ? 4 : 8;
   out.rs = (64 * C + dmax_search + 1 + align - 1) / align * align;
   const size_t tile = (size_t)n_sub * out.rs * dtype_size(store);
-  if (2 * tile <= kLdsBudget) { out.n_buf = 2; out.lds = 2 * tile; }
-  else if (tile <= kLdsBudget) { out.n_buf = 1; out.lds = tile; }
-  else return false;
-  return true;
+  out.n_buf = persistent_buffers(tile, NW);
+  out.lds = out.n_buf * tile;
+  return out.n_buf > 0;
 }
 
 // 16 waves when there are at least 16 DM trials, and 8.
@@ -1171,9 +1181,9 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
     }
     bc.n_cubes = (int)b->descs.size() - bc.first_desc;
     const size_t tile = (size_t)bc.buf_stride * sz;
-    if (tile > kLdsBudget)
+    bc.n_buf = persistent_buffers(tile, nw_b);
+    if (bc.n_buf == 0)
       return fail(NSFRB_ERR_UNSUPPORTED, "a batch cube's rows do not fit in LDS with 16-byte row pitches");
-    bc.n_buf = 2 * tile <= kLdsBudget ? 2 : 1;
     bc.lds = bc.n_buf * tile;
     b->n_items += bc.n_items;
   }

@@ -6,7 +6,7 @@
 namespace nsfrb {
 
 enum { DT_F32 = 0, DT_F16 = 1, DT_BF16 = 2 };
-enum { NORM_PIXEL_SUBBAND = 0, NORM_PIXEL = 1, NORM_EXTERNAL = 2, NORM_NONE = 3 };
+enum { NORM_PIXEL_SUBBAND = 0, NORM_EXTERNAL = 2, NORM_NONE = 3 };
 
 struct StatsLaunch {
   const void* x;

@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY",
                 4: "DEVICE", 5: "NOT_READY", 6: "TRUNCATED"}
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 DTYPE_BYTES = {"f32": 4, "f16": 2, "bf16": 2}
-NORMS = {"pixel_subband": 0, "pixel": 1, "external": 2, "none": 3}
+NORMS = {"pixel_subband": 0, "external": 2, "none": 3}
 LAYOUTS = {"tsp": 0, "pst": 1}
 
 # every symbol declared in include/nsfrb.h

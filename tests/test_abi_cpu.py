@@ -59,7 +59,6 @@ def test_valid_config_and_struct_size(L):
     (dict(dms=[0.0, -5.0]), nsfrb.INVALID_ARG, "DM"),
     (dict(dt_ms=0.0), nsfrb.INVALID_ARG, "dt_ms"),
     (dict(max_candidates=0), nsfrb.INVALID_ARG, "max_candidates"),
-    (dict(norm="pixel"), nsfrb.UNSUPPORTED, "PIXEL"),
     (dict(n_time=5000), nsfrb.UNSUPPORTED, "n_time"),
     (dict(snr_threshold=float("nan")), nsfrb.INVALID_ARG, "snr_threshold"),
 ])
@@ -67,6 +66,16 @@ def test_invalid_configs(L, kw, status, msg):
     c = c2_config(**kw)
     assert c.validate() == status
     assert msg in nsfrb.last_error()
+
+
+def test_unused_normalisation_value_is_refused(L):
+    """Value 1 of nsfrb_norm (statistics per pixel over all sub-bands) is not offered."""
+    for v in (1, -1, 4):
+        c = c2_config()
+        c.c.norm = v
+        assert c.validate() == nsfrb.INVALID_ARG
+        assert "normalisation" in nsfrb.last_error()
+    assert "pixel" not in nsfrb.NORMS
 
 
 @pytest.mark.parametrize("seed", range(4))
