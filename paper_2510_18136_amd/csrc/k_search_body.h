@@ -210,7 +210,7 @@ struct Reporter {
     const int l = lane_id();
     const bool act = l < NSFRB_NW;
     const float s = (act && snr_lane > kNegInf) ? snr_lane / norm_lane : kNegInf;
-    if (act) {
+    if (act && p < o.n_pix) {         // (a batch item's last pixels may lie past the cube)
       const size_t idx = ((size_t)d * NSFRB_NW + l) * o.n_pix + p;
       o.snr_max[idx] = s;
       o.toa[idx] = toa_lane;
@@ -491,16 +491,23 @@ __device__ __forceinline__ void search_pixel_dms(const CubeDesc& cd, const int* 
   }
 }
 
-// The per-pixel best (S/N, d, w, t) over the workgroup's waves; ends with a barrier.
-template <int NW>
-__device__ __forceinline__ void write_best(const CubeDesc& cd, int p, const Best& mine, Best* red, int wv, int l) {
+// The per-pixel best (S/N, d, w, t) of pixels p0 .. p0+PIX-1 (pixel k searched
+// by waves k*NW/PIX ..; pixels at or past n_pix are not written); starts with
+// a barrier.
+template <int NW, int PIX = 1>
+__device__ __forceinline__ void write_best(const CubeDesc& cd, int p0, const Best& mine, Best* red, int wv, int l) {
+  constexpr int WPP = NW / PIX;
   if (l == 0) red[wv] = mine;
   __syncthreads();
-  if (tid_x() == 0) {
-    Best b = red[0];
-    for (int w = 1; w < NW; ++w)
-      if (better(red[w].s, red[w].d, red[w].w, b)) b = red[w];
+  const int k = tid_x();
+  if (k < PIX && p0 + k < cd.n_pix) {
+    Best b = red[k * WPP];
+    for (int w = 1; w < WPP; ++w) {
+      const Best& o = red[k * WPP + w];
+      if (better(o.s, o.d, o.w, b)) b = o;
+    }
     const bool ok = b.s > kNegInf;
+    const int p = p0 + k;
     cd.best_s[p] = ok ? b.s : kNegInf;
     cd.best_d[p] = ok ? b.d : -1;
     cd.best_w[p] = ok ? b.w : -1;
@@ -579,21 +586,27 @@ __device__ __forceinline__ void search_persistent(const CubeDesc& cd, const int*
   __builtin_amdgcn_s_waitcnt(0);
 }
 
-// Persistent batch: the work items (one pixel each) of the cubes of one kernel
-// class, concatenated in cube order (descs[c].item_begin), walked as in
-// search_persistent. A workgroup's items increase, so its cube index only moves
-// forward; descriptors, delays and normalisers come through the scalar cache.
-// Cubes differ in n_sub, n_t, row pitch (rs) and delays: the -inf tails are
-// written for each item, and each cube's rows are copied with the widest lane
-// copy its alignment allows (dma_w). buf_stride: elements between the two LDS
-// buffers (the class's largest tile).
-template <int C, int NW, int NBUF>
+// Persistent batch: the work items of the cubes of one kernel class (PIX
+// consecutive pixels of one cube each; a cube's last item may run past its
+// pixels), concatenated in cube order (descs[c].item_begin), walked as in
+// search_persistent. A workgroup's items increase, so its cube index only
+// moves forward; descriptors, delays and normalisers come through the scalar
+// cache. Pixel k of an item is searched by waves k*NW/PIX .. (k+1)*NW/PIX - 1,
+// which split its DM trials. Cubes differ in n_sub, n_t, row pitch (rs) and
+// delays: the -inf tails are written for each item, and each cube's rows are
+// copied with the copy its alignment allows (dma_w). buf_stride: elements
+// between the LDS buffers (PIX tiles of the class's largest size each).
+template <int C, int NW, int NBUF, int PIX>
 __device__ __forceinline__ void search_batch_persistent(const CubeDesc* __restrict__ descs, int n_cubes,
                                                         long long n_items, int buf_stride) {
+  static_assert(NW % PIX == 0, "every pixel of an item gets the same number of waves");
+  constexpr int WPP = NW / PIX;
   extern __shared__ unsigned char lds_raw[];
   __shared__ Best red[NW];
   const int wv = __builtin_amdgcn_readfirstlane(tid_x() / kWave);
   const int l = lane_id();
+  const int slot = wv / WPP, wq = wv % WPP;
+  const int tile_stride = buf_stride / PIX;
   ST* bufs = reinterpret_cast<ST*>(lds_raw);
   auto cube_of = [&](long long i, int c) {
     while (c + 1 < n_cubes && i >= ld_const(&descs[c + 1].item_begin)) ++c;
@@ -601,8 +614,12 @@ __device__ __forceinline__ void search_batch_persistent(const CubeDesc* __restri
   };
   auto stage = [&](int c, long long i, ST* buf) {
     const CubeDesc cd = ld_const(descs + c);
-    fill_tails<NW>(buf, cd.n_sub, cd.n_t, cd.rs);
-    stage_rows_w<NW>(cd, (int)(i - cd.item_begin), buf, wv, l);
+    const int p0 = (int)(i - cd.item_begin) * PIX;
+#pragma unroll
+    for (int k = 0; k < PIX; ++k) {
+      fill_tails<NW>(buf + k * tile_stride, cd.n_sub, cd.n_t, cd.rs);
+      stage_rows_w<NW>(cd, min(p0 + k, cd.n_pix - 1), buf + k * tile_stride, wv, l);
+    }
   };
   const ItemWalk r = xcd_walk<NW>(n_items);
   long long k = r.k0, i = r.item(k);
@@ -610,23 +627,23 @@ __device__ __forceinline__ void search_batch_persistent(const CubeDesc* __restri
   if (i < r.n) stage(c, i, bufs);
   for (int it = 0; i < r.n; ++it) {
     const CubeDesc cd = ld_const(descs + c);
-    const int p = (int)(i - cd.item_begin);
+    const int p0 = (int)(i - cd.item_begin) * PIX;
     k += r.step;
     const long long i_next = r.item(k);
     const int c_next = i_next < r.n ? cube_of(i_next, c) : c;
-    ST* zl = bufs + (NBUF == 2 ? (it & 1) * buf_stride : 0);
+    ST* buf = bufs + (NBUF == 2 ? (it & 1) * buf_stride : 0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (NBUF == 2 && i_next < r.n) stage(c_next, i_next, bufs + ((it + 1) & 1) * buf_stride);
-    Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, p, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0,
+    Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, p0 + slot, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0,
                  lane_norm(cd, l)};
-    search_pixel_dms<C, NW>(cd, cd.delays, cd.dmax, zl, rep, wv, l, [&]() {
+    search_pixel_dms<C, WPP>(cd, cd.delays, cd.dmax, buf + slot * tile_stride, rep, wq, l, [&]() {
       if (NBUF == 1) {
         __syncthreads();   // no wave reads the rows of this item again
         if (i_next < r.n) stage(c_next, i_next, bufs);
       }
     });
-    write_best<NW>(cd, p, rep.best, red, wv, l);
+    write_best<NW, PIX>(cd, p0, rep.best, red, wv, l);
     c = c_next;
     i = i_next;
   }

@@ -300,11 +300,15 @@ static const char* store_type_name(int store) {
 struct PersistentKernel {
   int C, NW, n_buf;
 };
+// A persistent batch kernel: samples per lane, waves, LDS buffers, pixels per item.
+struct BatchKernel {
+  int C, NW, n_buf, pix;
+};
 // Translation unit with the per-DM kernels of `single` (C, PIX, NW), the
 // persistent single-cube kernels, and one persistent batch kernel per entry of
-// `batch` (C, LDS buffers in PIX, NW).
+// `batch`.
 static std::string gen_source(int store, int nw, int npass, const std::string& chain,
-                              const std::vector<KernelClass>& single, const std::vector<KernelClass>& batch,
+                              const std::vector<KernelClass>& single, const std::vector<BatchKernel>& batch,
                               const std::vector<PersistentKernel>& persistent = {}) {
   std::ostringstream o;
   o << "#define NSFRB_RTC_PROLOGUE 1\n#include \"device_common.h\"\n";
@@ -320,12 +324,12 @@ static std::string gen_source(int store, int nw, int npass, const std::string& c
     o << "extern \"C\" __global__ __launch_bounds__(" << 64 * k.NW << ") void nsfrb_persistent_c" << k.C << "_w"
       << k.NW << "_b" << k.n_buf << "(nsfrb::CubeDesc cd, const int* __restrict__ delays, const int* __restrict__ dmax"
       << ") { nsfrb::search_persistent<" << k.C << ", " << k.NW << ", " << k.n_buf << ">(cd, delays, dmax); }\n";
-  // one persistent kernel per class of the batch (PIX carries its LDS buffers)
+  // one persistent kernel per class of the batch
   for (size_t i = 0; i < batch.size(); ++i)
     o << "extern \"C\" __global__ __launch_bounds__(" << 64 * batch[i].NW << ") void nsfrb_batch_kernel_" << i
       << "(const nsfrb::CubeDesc* __restrict__ descs, int n_cubes, long long n_items, int buf_stride) {\n"
-         "  nsfrb::search_batch_persistent<" << batch[i].C << ", " << batch[i].NW << ", " << batch[i].PIX
-      << ">(descs, n_cubes, n_items, buf_stride);\n}\n";
+         "  nsfrb::search_batch_persistent<" << batch[i].C << ", " << batch[i].NW << ", " << batch[i].n_buf << ", "
+      << batch[i].pix << ">(descs, n_cubes, n_items, buf_stride);\n}\n";
   return o.str();
 }
 
@@ -490,11 +494,12 @@ extern "C" int nsfrb_debug_plan_source(const nsfrb_search_config* cfg, char* out
   if (gen_chain(std::vector<int>(cfg->width, cfg->width + cfg->n_width), chain, &npass, max_acc) != NSFRB_OK)
     return -1;
   std::vector<PersistentKernel> pks;
-  std::vector<KernelClass> bks;          // batch kernels of the same shapes (PIX carries the LDS buffers)
+  std::vector<BatchKernel> bks;          // batch kernels of the same shapes, one and two pixels per item
   for (const PersistentPlan& pp : persistent_candidates(cfg->n_dm, cfg->n_sub, cfg->n_time, C, dmax_search,
                                                         cfg->store_dtype)) {
     pks.push_back({C, pp.NW, pp.n_buf});
-    bks.push_back({C, pp.n_buf, pp.NW});
+    bks.push_back({C, pp.NW, pp.n_buf, 1});
+    bks.push_back({C, pp.NW, 1, 2});
   }
   const std::string src = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, bks, pks);
   if (out && cap > 0) std::snprintf(out, (size_t)cap, "%s", src.c_str());
@@ -1079,9 +1084,9 @@ extern "C" nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* i
 // One kernel class of a batch: the cubes with the same samples per lane (C) and
 // waves per workgroup; one persistent kernel walks all their pixels.
 struct BatchClass {
-  KernelClass k;                         // C, PIX = 1, NW
-  int n_buf = 1;                         // LDS pixel buffers
-  int buf_stride = 0;                    // elements between the buffers (the class's largest tile)
+  KernelClass k;                         // C, PIX (pixels per work item), NW
+  int n_buf = 1;                         // LDS buffers (PIX tiles each)
+  int buf_stride = 0;                    // elements between the buffers (PIX times the class's largest tile)
   hipFunction_t fn = nullptr;
   int first_desc = 0, n_cubes = 0;       // descriptors [first_desc, first_desc + n_cubes)
   long long n_items = 0;
@@ -1119,6 +1124,17 @@ static void batch_release(nsfrb_batch* b) {
   delete b;
 }
 
+// Pixels per batch work item (tile: one pixel's LDS rows in bytes). One by
+// default: on the 64-cube benchmark batch (8 DM trials) two and four pixels
+// per item measured 146 and 168 ms against 123 ms. NSFRB_BATCH_PIX = 2 or 4
+// asks for more (fewer barriers per pixel when a pixel's trials are few);
+// never more than fit in LDS.
+static int batch_pixels_per_item(int nw, int env, size_t tile) {
+  int pix = (env == 2 || env == 4) ? std::min(env, nw) : 1;
+  while (pix > 1 && (size_t)pix * tile > kLdsBudget) pix >>= 1;
+  return pix;
+}
+
 extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int32_t n_cubes, nsfrb_batch** out) {
   g_last_error.clear();
   if (!out || !cfgs || n_cubes < 1) return fail(NSFRB_ERR_INVALID_ARG, "need cfgs, n_cubes >= 1 and out");
@@ -1148,6 +1164,8 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
   // kernel classes: cubes with the same samples per lane; 16 waves when there
   // are at least 16 DM trials (the trials are shared by all cubes), else 8
   const int nw_b = c0.n_dm >= 16 ? 16 : 8;
+  int pix_env = 0;
+  if (const char* e = std::getenv("NSFRB_BATCH_PIX")) pix_env = std::atoi(e);
   const size_t sz = dtype_size(c0.store_dtype);
   const int align = c0.store_dtype == DT_F32 ? 4 : 8;          // row pitch: whole 16-byte vectors
   std::vector<int> cls_of(b->cubes.size());
@@ -1166,6 +1184,11 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
   b->desc_of_cube.assign(b->cubes.size(), -1);
   for (size_t c = 0; c < b->classes.size(); ++c) {
     BatchClass& bc = b->classes[c];
+    int tile1 = 0;                       // the class's largest one-pixel tile (elements)
+    for (size_t i = 0; i < b->cubes.size(); ++i)
+      if (cls_of[i] == (int)c)
+        tile1 = std::max(tile1, b->cubes[i]->cfg.n_sub * ((b->cubes[i]->rs + align - 1) / align * align));
+    bc.k.PIX = batch_pixels_per_item(nw_b, pix_env, (size_t)tile1 * sz);
     bc.first_desc = (int)b->descs.size();
     for (size_t i = 0; i < b->cubes.size(); ++i) {
       if (cls_of[i] != (int)c) continue;
@@ -1174,10 +1197,10 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
       d.rs = (h->rs + align - 1) / align * align;
       d.delays = h->d_delays_zeroed;
       d.item_begin = bc.n_items;
-      bc.n_items += h->n_pix;
+      bc.n_items += (h->n_pix + bc.k.PIX - 1) / bc.k.PIX;
       b->desc_of_cube[i] = (int)b->descs.size();
       b->descs.push_back(d);
-      bc.buf_stride = std::max(bc.buf_stride, h->cfg.n_sub * d.rs);
+      bc.buf_stride = std::max(bc.buf_stride, bc.k.PIX * h->cfg.n_sub * d.rs);
     }
     bc.n_cubes = (int)b->descs.size() - bc.first_desc;
     const size_t tile = (size_t)bc.buf_stride * sz;
@@ -1194,8 +1217,8 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
   nsfrb_status st = gen_chain(b->cubes[0]->widths, chain, &npass, max_acc);
   if (st != NSFRB_OK) return st;
   HIP_TRY(hipSetDevice(b->device));
-  std::vector<KernelClass> ks;
-  for (const auto& bc : b->classes) ks.push_back({bc.k.C, bc.n_buf, bc.k.NW});   // PIX carries the buffers
+  std::vector<BatchKernel> ks;
+  for (const auto& bc : b->classes) ks.push_back({bc.k.C, bc.k.NW, bc.n_buf, bc.k.PIX});
   st = load_module(b->device, gen_source(b->store, b->nw, npass, chain, {}, ks), &b->mod);
   if (st != NSFRB_OK) return st;
   int n_cu = 0;

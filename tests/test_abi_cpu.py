@@ -109,7 +109,8 @@ def test_forced_allocation_failure(L, monkeypatch):
 def test_chain_plan_composes_non_power_of_two_widths(L):
     src = c2_config().plan_source()
     assert "nsfrb_search_c33_p1_w8" in src and "search_cube<33, 1, 8>" in src and "search_cube<33, 1, 16>" in src
-    assert "nsfrb_persistent_c33_w16_b1" in src and "search_batch_persistent<33, 16, 1>" in src
+    assert "nsfrb_persistent_c33_w16_b1" in src and "search_batch_persistent<33, 16, 1, 1>" in src
+    assert "search_batch_persistent<33, 8, 1, 2>" in src
     # 1200 = 16 + 32 + 128 + 1024 placed end to end: offsets 16, 48, 176
     for frag in ("copy_arr(acc0, a0)", "shift_add<16>(acc0", "shift_add<48>(acc0", "shift_add<176>(acc0",
                  "rep(11, acc0)"):

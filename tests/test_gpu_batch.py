@@ -192,6 +192,41 @@ def test_batch_row_copies_of_every_alignment():
     assert ntot == o["n_total"]
 
 
+@pytest.mark.parametrize("pix", [1, 2, 4])
+def test_batch_pixels_per_item(monkeypatch, pix):
+    """Work items of 1, 2 or 4 pixels (NSFRB_BATCH_PIX), on cubes whose pixel
+    counts are odd (the last item of a cube runs past it): maps, per-pixel best
+    and candidates bitwise equal to one plain launch per cube."""
+    monkeypatch.setenv("NSFRB_BATCH_PIX", str(pix))
+    widths = [1, 2, 4, 8, 16]
+    cases = [(7, 5, 8, 256), (9, 9, 16, 100), (13, 3, 8, 333), (4, 4, 16, 64)]
+    stream = torch.cuda.current_stream().cuda_stream
+    cfgs, cubes = [], []
+    for k, (nx, ny, ns, nt) in enumerate(cases):
+        c = nsfrb.SearchConfig(nx, ny, nt, np.linspace(1.311, 1.499, ns), C1_DMS, widths, in_dtype="f16",
+                               store_dtype="f16", norm="none", layout="pst", snr_threshold=5.0, max_candidates=16)
+        x = torch.empty(nx * ny * ns * nt, dtype=torch.float16, device="cuda")
+        nsfrb.generate_noise(x.data_ptr(), "f16", "pst", nx * ny, ns, nt, 900 + k, stream=stream)
+        off = delay_table(c.freqs, c.freqs.max(), 134.2, [500.0])[0]
+        nsfrb.inject_boxcar(x.data_ptr(), "f16", "pst", nx * ny, ns, nt, pixel=nx * ny - 1, t0=20,
+                            width=4, amp=3.0, offsets=off, stream=stream)
+        cfgs.append(c)
+        cubes.append(x)
+    ptrs = [x.data_ptr() for x in cubes]
+    print(f"[gpu] batch with {pix} pixel(s) per item", flush=True)
+    with nsfrb.Batch(cfgs) as b:
+        b.run_separate(ptrs, stream)
+        ref = results(b, len(cfgs))
+        ref_best = [b.best(i) for i in range(len(cfgs))]
+        b.run(ptrs, stream)
+        same(results(b, len(cfgs)), ref)
+        for i in range(len(cfgs)):
+            for g, r in zip(b.best(i), ref_best[i]):
+                assert np.array_equal(g, r, equal_nan=True)
+    for i, (snr, toa, cands, ntot) in enumerate(ref):     # the pulse sits on each cube's last pixel
+        assert ntot >= 1 and cands[0]["x"] + cfgs[i].nx * cands[0]["y"] == cfgs[i].n_pix - 1
+
+
 def test_injectors_match_their_definition():
     """Batched boxcars and interference added to zero cubes equal the definition
     written out in NumPy (FP32 adds to zero are exact), in both layouts."""
