@@ -71,8 +71,17 @@ def algorithmic_counts(n_pix, n_sub, n_t, delays, widths, store_bytes):
 
 
 def kernel_source_hash():
+    """Hash of the code of the survey's kernels: the generated search source of
+    the survey plan (FP32 and FP16 store) with the headers it includes, and the
+    ahead-of-time statistics and candidate kernels. Counter figures taken for
+    other code are stale."""
+    from paper_2510_18136_amd import nsfrb, synth
     h = hashlib.sha256()
-    for fn in ("k_search_body.h", "device_common.h", "k_stats.hip", "k_cand.hip", "nsfrb.cpp"):
+    freqs, dms, widths = synth.config2_grid()
+    for store in ("f32", "f16"):
+        cfg = nsfrb.SearchConfig(256, 256, 2048, freqs, dms, widths, store_dtype=store)
+        h.update(cfg.plan_source().encode())
+    for fn in ("k_search_body.h", "device_common.h", "k_stats.hip", "k_cand.hip"):
         h.update(open(os.path.join(ROOT, "paper_2510_18136_amd", "csrc", fn), "rb").read())
     return h.hexdigest()[:16]
 

@@ -517,7 +517,10 @@ struct nsfrb_search {
   std::vector<int32_t> widths, delays, dmaxv;
   int n_pix = 0, device = 0;
   int C = 0, rs = 0, pix = 1, nw = 8;  // chosen kernel class and LDS row length
+  int dmax_search = 0;                 // largest delay of a searchable trial
   int max_acc = kMaxAccumulators;      // accumulators per pass of the boxcar plan (no register spills)
+  std::vector<KernelClass> cands;      // per-DM shapes that fit LDS
+  bool planned = false;                // kernels compiled and tuned (a batch's cubes plan on first separate run)
   size_t lds_bytes = 0;
   std::string source;                  // generated search translation unit
   hipModule_t mod = nullptr;
@@ -579,32 +582,11 @@ static void release(nsfrb_search* h) {
 
 static nsfrb_status autotune(nsfrb_search* h, const std::vector<KernelClass>& ks);
 
-extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfrb_search** out) {
-  g_last_error.clear();
-  if (!out) return fail(NSFRB_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  nsfrb_status st = validate(cfg);
-  if (st != NSFRB_OK) return st;
-  std::unique_ptr<nsfrb_search, void (*)(nsfrb_search*)> h(new nsfrb_search, release);
-  h->cfg = *cfg;
-  h->freqs.assign(cfg->freq_ghz, cfg->freq_ghz + cfg->n_sub);
-  h->dms.assign(cfg->dm, cfg->dm + cfg->n_dm);
-  h->widths.assign(cfg->width, cfg->width + cfg->n_width);
-  h->cfg.freq_ghz = h->freqs.data();
-  h->cfg.dm = h->dms.data();
-  h->cfg.width = h->widths.data();
-  h->n_pix = cfg->nx * cfg->ny;
-  h->device = cfg->device;
-  compute_delays(h->cfg, h->delays);
-  const int dmax_search = max_delay_searchable(h->delays, cfg->n_dm, cfg->n_sub, cfg->n_time, &h->dmaxv);
-  h->C = samples_per_lane(cfg->n_time, cfg->store_dtype);
-  h->rs = row_len(h->C, dmax_search, cfg->store_dtype);
-  std::vector<KernelClass> ks = plan_candidates(h->C, cfg->n_dm, cfg->n_sub, h->rs, cfg->store_dtype);
-  if (ks.empty())
-    return fail(NSFRB_ERR_UNSUPPORTED, "n_sub x (padded n_time + max delay) does not fit in LDS for this store dtype");
-  const char* force = std::getenv("NSFRB_FORCE_ALLOC_FAIL");
-  if (force && std::atoi(force) != 0) return fail(NSFRB_ERR_OUT_OF_MEMORY, "allocation failure forced by NSFRB_FORCE_ALLOC_FAIL");
-
+// Compiles the handle's kernels (dropping shapes that would spill), sizes the
+// persistent grids and runs the autotuner.
+static nsfrb_status plan_kernels(nsfrb_search* h) {
+  const nsfrb_search_config* cfg = &h->cfg;
+  nsfrb_status st = NSFRB_OK;
   HIP_TRY(hipSetDevice(h->device));
   // Only kernels that keep the boxcar chain in registers (up to a few dozen
   // bytes of spill) are ever launched: each compiled candidate's scratch use is
@@ -623,15 +605,15 @@ extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfr
     if (st != NSFRB_OK) return st;
     std::vector<PersistentPlan> pps;
     if (pers_only != 0)
-      for (const PersistentPlan& pp : persistent_candidates(cfg->n_dm, cfg->n_sub, cfg->n_time, h->C, dmax_search,
+      for (const PersistentPlan& pp : persistent_candidates(cfg->n_dm, cfg->n_sub, cfg->n_time, h->C, h->dmax_search,
                                                             cfg->store_dtype))
         if (pers_only < 0 || pp.NW == pers_only) pps.push_back(pp);
     std::vector<PersistentKernel> pks;
     for (const PersistentPlan& pp : pps) pks.push_back({h->C, pp.NW, pp.n_buf});
-    h->source = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, ks, {}, pks);
+    h->source = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, h->cands, {}, pks);
     st = load_module(h->device, h->source, &h->mod);
     if (st != NSFRB_OK) return st;
-    for (const KernelClass& k : ks) {
+    for (const KernelClass& k : h->cands) {
       hipFunction_t fn = nullptr;
       HIP_TRY(hipModuleGetFunction(&fn, h->mod, single_kernel_name(k).c_str()));
       int scratch = 0;
@@ -656,7 +638,50 @@ extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfr
                                            " samples per lane and these widths would spill more than " +
                                            std::to_string(allowance) +
                                            " bytes of registers per lane (n_time too long for the width list)");
-  ks = usable;
+  int n_cu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device));
+  h->pers_grids.clear();
+  for (size_t i = 0; i < h->pers_plans.size(); ++i) {
+    int per_cu = 0;
+    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, h->pers_fns[i], 64 * h->pers_plans[i].NW,
+                                                               h->pers_plans[i].lds));
+    h->pers_grids.push_back((unsigned)(std::max(1, n_cu) * std::max(1, per_cu)));
+  }
+  st = autotune(h, usable);
+  if (st != NSFRB_OK) return st;
+  h->lds_bytes = lds_bytes_for(h->pix, cfg->n_sub, h->rs, cfg->store_dtype);
+  h->planned = true;
+  return NSFRB_OK;
+}
+
+// A handle with its buffers; its kernels are planned now or (plan_now false,
+// for a batch's cubes) before its first separate launch.
+static nsfrb_status search_create(const nsfrb_search_config* cfg, bool plan_now, nsfrb_search** out) {
+  if (!out) return fail(NSFRB_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  nsfrb_status st = validate(cfg);
+  if (st != NSFRB_OK) return st;
+  std::unique_ptr<nsfrb_search, void (*)(nsfrb_search*)> h(new nsfrb_search, release);
+  h->cfg = *cfg;
+  h->freqs.assign(cfg->freq_ghz, cfg->freq_ghz + cfg->n_sub);
+  h->dms.assign(cfg->dm, cfg->dm + cfg->n_dm);
+  h->widths.assign(cfg->width, cfg->width + cfg->n_width);
+  h->cfg.freq_ghz = h->freqs.data();
+  h->cfg.dm = h->dms.data();
+  h->cfg.width = h->widths.data();
+  h->n_pix = cfg->nx * cfg->ny;
+  h->device = cfg->device;
+  compute_delays(h->cfg, h->delays);
+  h->dmax_search = max_delay_searchable(h->delays, cfg->n_dm, cfg->n_sub, cfg->n_time, &h->dmaxv);
+  h->C = samples_per_lane(cfg->n_time, cfg->store_dtype);
+  h->rs = row_len(h->C, h->dmax_search, cfg->store_dtype);
+  h->cands = plan_candidates(h->C, cfg->n_dm, cfg->n_sub, h->rs, cfg->store_dtype);
+  if (h->cands.empty())
+    return fail(NSFRB_ERR_UNSUPPORTED, "n_sub x (padded n_time + max delay) does not fit in LDS for this store dtype");
+  const char* force = std::getenv("NSFRB_FORCE_ALLOC_FAIL");
+  if (force && std::atoi(force) != 0) return fail(NSFRB_ERR_OUT_OF_MEMORY, "allocation failure forced by NSFRB_FORCE_ALLOC_FAIL");
+
+  HIP_TRY(hipSetDevice(h->device));
   const size_t n_pix = (size_t)h->n_pix, ns = (size_t)cfg->n_sub, nt = (size_t)cfg->n_time;
   const size_t nmaps = (size_t)cfg->n_dm * cfg->n_width * n_pix;
   HIP_TRY(dalloc(&h->d_delays, h->delays.size()));
@@ -698,19 +723,17 @@ extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfr
     HIP_TRY(dalloc(&h->d_delays_zeroed, dz.size()));
     HIP_TRY(hipMemcpy(h->d_delays_zeroed, dz.data(), dz.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   }
-  int n_cu = 0;
-  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device));
-  for (size_t i = 0; i < h->pers_plans.size(); ++i) {
-    int per_cu = 0;
-    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, h->pers_fns[i], 64 * h->pers_plans[i].NW,
-                                                               h->pers_plans[i].lds));
-    h->pers_grids.push_back((unsigned)(std::max(1, n_cu) * std::max(1, per_cu)));
+  if (plan_now) {
+    st = plan_kernels(h.get());
+    if (st != NSFRB_OK) return st;
   }
-  st = autotune(h.get(), ks);
-  if (st != NSFRB_OK) return st;
-  h->lds_bytes = lds_bytes_for(h->pix, cfg->n_sub, h->rs, cfg->store_dtype);
   *out = h.release();
   return NSFRB_OK;
+}
+
+extern "C" nsfrb_status nsfrb_search_create(const nsfrb_search_config* cfg, nsfrb_search** out) {
+  g_last_error.clear();
+  return search_create(cfg, true, out);
 }
 
 extern "C" nsfrb_status nsfrb_search_destroy(nsfrb_search* h) {
@@ -1157,7 +1180,7 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
   b->nw = c0.n_width;
   for (int i = 0; i < n_cubes; ++i) {
     nsfrb_search* h = nullptr;
-    nsfrb_status st = nsfrb_search_create(&cfgs[i], &h);
+    nsfrb_status st = search_create(&cfgs[i], false, &h);
     if (st != NSFRB_OK) return fail(st, "cube " + std::to_string(i) + ": " + g_last_error);
     b->cubes.push_back(h);
   }
@@ -1210,27 +1233,36 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
     bc.lds = bc.n_buf * tile;
     b->n_items += bc.n_items;
   }
-  std::string chain;
-  int npass = 1;
-  int max_acc = kMaxAccumulators;
-  for (const nsfrb_search* h : b->cubes) max_acc = std::min(max_acc, h->max_acc);
-  nsfrb_status st = gen_chain(b->cubes[0]->widths, chain, &npass, max_acc);
-  if (st != NSFRB_OK) return st;
+  // one module with a persistent kernel per class; like a single cube's plan it
+  // is regenerated with fewer accumulators per pass while a class kernel would
+  // spill more than a search kernel may, and refused only after that
   HIP_TRY(hipSetDevice(b->device));
-  std::vector<BatchKernel> ks;
-  for (const auto& bc : b->classes) ks.push_back({bc.k.C, bc.k.NW, bc.n_buf, bc.k.PIX});
-  st = load_module(b->device, gen_source(b->store, b->nw, npass, chain, {}, ks), &b->mod);
-  if (st != NSFRB_OK) return st;
   int n_cu = 0;
   HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, b->device));
+  std::vector<BatchKernel> ks;
+  for (const auto& bc : b->classes) ks.push_back({bc.k.C, bc.k.NW, bc.n_buf, bc.k.PIX});
+  bool fits = false;
+  for (int max_acc = kMaxAccumulators; max_acc >= 1 && !fits; --max_acc) {
+    std::string chain;
+    int npass = 1;
+    nsfrb_status st = gen_chain(b->cubes[0]->widths, chain, &npass, max_acc);
+    if (st != NSFRB_OK) return st;
+    st = load_module(b->device, gen_source(b->store, b->nw, npass, chain, {}, ks), &b->mod);
+    if (st != NSFRB_OK) return st;
+    fits = true;
+    for (size_t c = 0; c < b->classes.size(); ++c) {
+      BatchClass& bc = b->classes[c];
+      HIP_TRY(hipModuleGetFunction(&bc.fn, b->mod, ("nsfrb_batch_kernel_" + std::to_string(c)).c_str()));
+      int scratch = 0;
+      HIP_TRY(hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, bc.fn));
+      fits = fits && scratch <= scratch_allowance();
+    }
+  }
+  if (!fits)
+    return fail(NSFRB_ERR_UNSUPPORTED, "a class's persistent kernel would spill more registers than a search kernel "
+                                       "may at every accumulator count");
   for (size_t c = 0; c < b->classes.size(); ++c) {
     BatchClass& bc = b->classes[c];
-    HIP_TRY(hipModuleGetFunction(&bc.fn, b->mod, ("nsfrb_batch_kernel_" + std::to_string(c)).c_str()));
-    int scratch = 0;
-    HIP_TRY(hipFuncGetAttribute(&scratch, HIP_FUNC_ATTRIBUTE_LOCAL_SIZE_BYTES, bc.fn));
-    if (scratch > scratch_allowance())
-      return fail(NSFRB_ERR_UNSUPPORTED, "the persistent kernel of class " + std::to_string(c) +
-                                             " would spill more registers than a search kernel may");
     // a persistent grid of as many workgroups as this class's kernel keeps resident
     int per_cu = 0;
     HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bc.fn, 64 * bc.k.NW, bc.lds));
@@ -1366,6 +1398,13 @@ extern "C" nsfrb_status nsfrb_batch_run_separate(nsfrb_batch* b, const void* con
   if (!b || !d_cubes) return fail(NSFRB_ERR_INVALID_ARG, "batch and d_cubes must be non-NULL");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(b->device));
+  // first separate run: compile and tune each cube's own kernels (synchronous;
+  // the tuner's launches finish before this run's work is enqueued)
+  for (auto* h : b->cubes)
+    if (!h->planned) {
+      nsfrb_status s = plan_kernels(h);
+      if (s != NSFRB_OK) return s;
+    }
   nsfrb_status s = batch_stats(b, d_cubes, st);
   if (s != NSFRB_OK) return s;
   for (auto* h : b->cubes) {

@@ -102,6 +102,11 @@ def config1(seed=0, amp=1.0, t0=20, width=4, dm=500.0, pixel=(16, 16)):
     return cube, meta
 
 
+def config2_grid(ns=16, n_dm=32, dm_max=4000.0):
+    """The survey search's sub-band centres (GHz), DM trials and widths."""
+    return np.linspace(1.311, 1.499, ns), np.linspace(0.0, dm_max, n_dm), widths_pow2(1024, (1200,))
+
+
 def config2(seed=2, nx=256, ny=256, nt=2048, ns=16, n_pulses=100, n_spikes=20,
             n_stripes=2, rfi_sigma=5.0, n_dm=32, dm_max=4000.0):
     """Survey-shape search: 256x256 px, 16 sub-bands, 2048 samples, pulses and RFI.
@@ -111,7 +116,7 @@ def config2(seed=2, nx=256, ny=256, nt=2048, ns=16, n_pulses=100, n_spikes=20,
     amplitude S/N * sigma_p / sqrt(width * n_sub); zero-DM spikes of 5 sigma_p
     per sub-band; full-duration sub-band stripes of 5 sigma_p.
     """
-    freqs = np.linspace(1.311, 1.499, ns)
+    freqs, dms, widths = config2_grid(ns, n_dm, dm_max)
     f_ref = float(freqs.max())
     npix = nx * ny
     rng = np.random.default_rng(seed + 1_000_003)
@@ -135,8 +140,7 @@ def config2(seed=2, nx=256, ny=256, nt=2048, ns=16, n_pulses=100, n_spikes=20,
     stripes = rng.choice(ns, size=n_stripes, replace=False)
     for s in stripes:
         stripe(cube, int(s), rfi_sigma * sig)
-    meta = dict(nx=nx, ny=ny, freqs=freqs, f_ref=f_ref, dt_ms=DT_MS,
-                dms=np.linspace(0.0, dm_max, n_dm), widths=widths_pow2(1024, (1200,)),
+    meta = dict(nx=nx, ny=ny, freqs=freqs, f_ref=f_ref, dt_ms=DT_MS, dms=dms, widths=widths,
                 theta=6.0, sigma_pix=sig, injections=inj, spikes=spikes, stripes=stripes)
     return cube, meta
 
