@@ -194,8 +194,10 @@ nsfrb_status nsfrb_stage_times_get(nsfrb_search* h, float* ms3);
  * workgroup, info[4] threads per workgroup, info[5] 1 if the persistent kernel
  * (one pixel per workgroup at a time, next pixel's rows loaded during the
  * search of the current one) was chosen, else 0; for it, info[6] LDS pixel
- * buffers and info[7] workgroups (0 otherwise); info[8] is 0. `info` holds 9
- * values. */
+ * buffers and info[7] workgroups (0 otherwise); info[8] is 1 if that kernel is
+ * the staggered form (the upper half of its waves searches the last DM
+ * round's boxcars of a pixel at the start of the next one), else 0. `info`
+ * holds 9 values. */
 nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* info);
 
 /* ---------------------------------------------------------- multi-timescale

@@ -586,6 +586,114 @@ __device__ __forceinline__ void search_persistent(const CubeDesc& cd, const int*
   __builtin_amdgcn_s_waitcnt(0);
 }
 
+// Staggered persistent form (one chain pass per DM round): as search_persistent,
+// but the waves come in two halves half a step apart. All waves of a workgroup
+// start a pixel together; without the stagger they all de-disperse at once
+// (bound by LDS bandwidth, the VALU half idle) and then all run chains (bound
+// by the VALU, the LDS idle). Here every wave runs the same steps, one
+// de-dispersion and one boxcar chain each, but the early half de-disperses a
+// DM and then searches it while the late half first searches the DM it
+// de-dispersed in its previous step (for the first step of a pixel, the last
+// DM of the previous pixel) and then de-disperses the next: at any time one
+// half reads rows while the other runs a chain. The series in flight stays in
+// the same registers (`cur`) from de-dispersion to chain, so the register
+// budget is the per-DM kernel's. A pixel's best is complete only after the late
+// half's first step of the next pixel, so it is reduced one barrier later
+// (double-buffered `red`).
+template <int C, int NW, int NBUF>
+__device__ __forceinline__ void search_persistent_staggered(const CubeDesc& cd, const int* __restrict__ delays,
+                                                            const int* __restrict__ dmaxv) {
+  static_assert(NSFRB_NPASS == 1, "a deferred chain needs the de-dispersed series of a single pass");
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ Best red[2][NW];
+  const int wv = __builtin_amdgcn_readfirstlane(tid_x() / kWave);
+  const int l = lane_id();
+  const bool late = wv >= NW / 2;
+  const int n_dm = cd.n_dm, n_t = cd.n_t, n_sub = cd.n_sub, rs = cd.rs;
+  const int n_rounds = (n_dm + NW - 1) / NW;
+  const int tile = n_sub * rs;
+  ST* bufs = reinterpret_cast<ST*>(lds_raw);
+  for (int b = 0; b < NBUF; ++b) fill_tails<NW>(bufs + b * tile, n_sub, n_t, rs);
+  const float norm_l = lane_norm(cd, l);
+  auto reduce_best = [&](int slot, int q) {      // thread 0: pixel q's best from the waves' bests
+    Best b = red[slot][0];
+    for (int w = 1; w < NW; ++w)
+      if (better(red[slot][w].s, red[slot][w].d, red[slot][w].w, b)) b = red[slot][w];
+    const bool ok = b.s > kNegInf;
+    cd.best_s[q] = ok ? b.s : kNegInf;
+    cd.best_d[q] = ok ? b.d : -1;
+    cd.best_w[q] = ok ? b.w : -1;
+    cd.best_t[q] = ok ? b.t : -1;
+  };
+  float cur[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) cur[c] = 0.f;
+  int cur_p = cd.n_pix, cur_d = 0;               // what cur holds (a late wave's series in flight)
+  int it = 0, p_prev = -1;
+  Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, 0, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0, norm_l};
+  auto dedisperse = [&](const ST* zl, int p, int step, int it, long long i_next) {
+    const int d = min(step * NW + wv, n_dm - 1);
+    const int* dd = delays + (size_t)d * n_sub;
+#pragma unroll
+    for (int c = 0; c < C; ++c) cur[c] = 0.f;
+    for (int s = 0; s < n_sub; ++s) add_row<C>(cur, zl + s * rs, ld_const(dd + s), l);
+    cur_p = p;
+    cur_d = d;
+    if (step == n_rounds - 1) {
+      // every wave has read this pixel's rows for the last time, and the late
+      // half has reported the previous pixel: its best is complete
+      __syncthreads();
+      if (it > 0 && tid_x() == 0) reduce_best((it - 1) & 1, p_prev);
+      if (NBUF == 1 && i_next >= 0) stage_rows_async<NW>(cd, (int)i_next, bufs, wv, l);
+    }
+  };
+  auto search = [&]() {                          // the boxcar chain of cur, reported for (cur_p, cur_d)
+    rep.p = cur_p;
+    nsfrb_chain<C>(0, cur, rep);
+    const bool searched = ld_const(dmaxv + cur_d) < n_t;
+    rep.d = cur_d;
+    rep.snr_lane = searched ? rep.snr_lane : kNegInf;
+    rep.toa_lane = searched ? rep.toa_lane : -1;
+    rep.flush();
+  };
+  const ItemWalk r = xcd_walk<NW>(cd.n_pix);
+  long long k = r.k0, i = r.item(k);
+  if (i < r.n) stage_rows_async<NW>(cd, (int)i, bufs, wv, l);
+  for (; i < r.n; ++it) {
+    const int p = (int)i;
+    k += r.step;
+    const long long i_next = r.item(k);
+    const ST* zl = bufs + (NBUF == 2 ? (it & 1) * tile : 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (NBUF == 2 && i_next < r.n) stage_rows_async<NW>(cd, (int)i_next, bufs + ((it + 1) & 1) * tile, wv, l);
+    for (int step = 0; step < n_rounds; ++step) {
+      if (!late) dedisperse(zl, p, step, it, NBUF == 1 && i_next < r.n ? i_next : -1);
+      search();
+      if (late && step == 0) {                   // the late half's part of the previous pixel is done
+        if (l == 0 && p_prev >= 0) red[(it - 1) & 1][wv] = rep.best;
+        rep.best = Best{kNegInf, -1, -1, -1};
+      }
+      if (late) dedisperse(zl, p, step, it, NBUF == 1 && i_next < r.n ? i_next : -1);
+    }
+    if (!late) {                                 // the early half's part of this pixel is done
+      if (l == 0) red[it & 1][wv] = rep.best;
+      rep.best = Best{kNegInf, -1, -1, -1};
+    }
+    p_prev = p;
+    i = i_next;
+  }
+  if (p_prev >= 0) {                             // the late half's last series, then the last pixel's best
+    if (late) {
+      search();
+      if (l == 0) red[(it - 1) & 1][wv] = rep.best;
+    }
+    __syncthreads();
+    if (tid_x() == 0) reduce_best((it - 1) & 1, p_prev);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
 // Persistent batch: the work items of the cubes of one kernel class (PIX
 // consecutive pixels of one cube each; a cube's last item may run past its
 // pixels), concatenated in cube order (descs[c].item_begin), walked as in

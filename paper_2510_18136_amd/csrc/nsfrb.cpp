@@ -299,6 +299,7 @@ static const char* store_type_name(int store) {
 // A persistent kernel to instantiate: samples per lane, waves, LDS buffers.
 struct PersistentKernel {
   int C, NW, n_buf;
+  bool stagger;                          // late half of the waves defers its last chain (one chain pass only)
 };
 // A persistent batch kernel: samples per lane, waves, LDS buffers, pixels per item.
 struct BatchKernel {
@@ -322,8 +323,10 @@ static std::string gen_source(int store, int nw, int npass, const std::string& c
       << "(nsfrb::CubeDesc cd) { search_cube<" << k.C << ", " << k.PIX << ", " << k.NW << ">(cd); }\n";
   for (const auto& k : persistent)
     o << "extern \"C\" __global__ __launch_bounds__(" << 64 * k.NW << ") void nsfrb_persistent_c" << k.C << "_w"
-      << k.NW << "_b" << k.n_buf << "(nsfrb::CubeDesc cd, const int* __restrict__ delays, const int* __restrict__ dmax"
-      << ") { nsfrb::search_persistent<" << k.C << ", " << k.NW << ", " << k.n_buf << ">(cd, delays, dmax); }\n";
+      << k.NW << "_b" << k.n_buf << (k.stagger ? "_s" : "")
+      << "(nsfrb::CubeDesc cd, const int* __restrict__ delays, const int* __restrict__ dmax) { nsfrb::"
+      << (k.stagger ? "search_persistent_staggered<" : "search_persistent<") << k.C << ", " << k.NW << ", "
+      << k.n_buf << ">(cd, delays, dmax); }\n";
   // one persistent kernel per class of the batch
   for (size_t i = 0; i < batch.size(); ++i)
     o << "extern \"C\" __global__ __launch_bounds__(" << 64 * batch[i].NW << ") void nsfrb_batch_kernel_" << i
@@ -431,6 +434,7 @@ static std::vector<KernelClass> plan_candidates(int C, int n_dm, int n_sub, int 
 // multiple of 16, pitch padded to 16 bytes), in one or two LDS buffers.
 struct PersistentPlan {
   int NW = 16, rs = 0, n_buf = 1;
+  bool stagger = false;                  // search_persistent_staggered
   size_t lds = 0;
 };
 
@@ -469,7 +473,8 @@ static std::vector<PersistentPlan> persistent_candidates(int n_dm, int n_sub, in
 }
 
 static std::string persistent_kernel_name(int C, const PersistentPlan& pp) {
-  return "nsfrb_persistent_c" + std::to_string(C) + "_w" + std::to_string(pp.NW) + "_b" + std::to_string(pp.n_buf);
+  return "nsfrb_persistent_c" + std::to_string(C) + "_w" + std::to_string(pp.NW) + "_b" + std::to_string(pp.n_buf) +
+         (pp.stagger ? "_s" : "");
 }
 
 // Host-only entry: generate (and optionally compile) the specialised search
@@ -497,7 +502,8 @@ extern "C" int nsfrb_debug_plan_source(const nsfrb_search_config* cfg, char* out
   std::vector<BatchKernel> bks;          // batch kernels of the same shapes, one and two pixels per item
   for (const PersistentPlan& pp : persistent_candidates(cfg->n_dm, cfg->n_sub, cfg->n_time, C, dmax_search,
                                                         cfg->store_dtype)) {
-    pks.push_back({C, pp.NW, pp.n_buf});
+    pks.push_back({C, pp.NW, pp.n_buf, false});
+    if (npass == 1) pks.push_back({C, pp.NW, pp.n_buf, true});
     bks.push_back({C, pp.NW, pp.n_buf, 1});
     bks.push_back({C, pp.NW, 1, 2});
   }
@@ -607,9 +613,15 @@ static nsfrb_status plan_kernels(nsfrb_search* h) {
     if (pers_only != 0)
       for (const PersistentPlan& pp : persistent_candidates(cfg->n_dm, cfg->n_sub, cfg->n_time, h->C, h->dmax_search,
                                                             cfg->store_dtype))
-        if (pers_only < 0 || pp.NW == pers_only) pps.push_back(pp);
+        if (pers_only < 0 || pp.NW == pers_only) {
+          pps.push_back(pp);
+          if (npass == 1) {              // the staggered form keeps one pass's series across pixels
+            pps.push_back(pp);
+            pps.back().stagger = true;
+          }
+        }
     std::vector<PersistentKernel> pks;
-    for (const PersistentPlan& pp : pps) pks.push_back({h->C, pp.NW, pp.n_buf});
+    for (const PersistentPlan& pp : pps) pks.push_back({h->C, pp.NW, pp.n_buf, pp.stagger});
     h->source = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, h->cands, {}, pks);
     st = load_module(h->device, h->source, &h->mod);
     if (st != NSFRB_OK) return st;
@@ -811,14 +823,14 @@ static nsfrb_status launch_search(const nsfrb_search* h, const void* z, hipStrea
 struct TuneKey {
   int C, n_sub, n_t, n_dm, n_pix_bucket, store;
   std::vector<int32_t> widths;
-  std::vector<int32_t> pers_nw;
+  std::vector<int32_t> pers;    // the persistent candidates: 2 NW + (staggered)
   bool operator<(const TuneKey& o) const {
-    return std::tie(C, n_sub, n_t, n_dm, n_pix_bucket, store, widths, pers_nw) <
-           std::tie(o.C, o.n_sub, o.n_t, o.n_dm, o.n_pix_bucket, o.store, o.widths, o.pers_nw);
+    return std::tie(C, n_sub, n_t, n_dm, n_pix_bucket, store, widths, pers) <
+           std::tie(o.C, o.n_sub, o.n_t, o.n_dm, o.n_pix_bucket, o.store, o.widths, o.pers);
   }
 };
 struct TuneChoice {
-  int pix, nw, pers_nw;   // pers_nw 0: the per-DM kernel is used
+  int pix, nw, pers;      // pers: index of the persistent candidate used, -1 for the per-DM kernel
 };
 static std::mutex g_tune_mu;
 static std::map<TuneKey, TuneChoice> g_tune_cache;
@@ -829,11 +841,7 @@ static nsfrb_status autotune(nsfrb_search* h, const std::vector<KernelClass>& ks
   for (size_t i = 0; i < ks.size(); ++i)
     HIP_TRY(hipModuleGetFunction(&fns[i], h->mod, single_kernel_name(ks[i]).c_str()));
   auto choose = [&](size_t i) { h->pix = ks[i].PIX; h->nw = ks[i].NW; h->search_fn = fns[i]; };
-  auto choose_pers = [&](int nw) {
-    h->pers = -1;
-    for (size_t i = 0; i < h->pers_plans.size(); ++i)
-      if (h->pers_plans[i].NW == nw) h->pers = (int)i;
-  };
+  auto choose_pers = [&](int i) { h->pers = (i >= 0 && i < (int)h->pers_plans.size()) ? i : -1; };
   choose(0);
   h->pers = -1;
   // NSFRB_PLAN="pixels,waves" picks that per-DM shape when it is a candidate (for tuning studies)
@@ -843,22 +851,26 @@ static nsfrb_status autotune(nsfrb_search* h, const std::vector<KernelClass>& ks
       for (size_t i = 0; i < ks.size(); ++i)
         if (ks[i].PIX == pp && ks[i].NW == ww) { choose(i); return NSFRB_OK; }
   }
-  // NSFRB_PERSISTENT=NW (NW > 0) keeps that persistent kernel (for studies)
+  // NSFRB_PERSISTENT=NW (NW > 0) keeps that persistent kernel, "NWs" its staggered form (for studies)
   if (const char* pe = std::getenv("NSFRB_PERSISTENT"))
-    if (std::atoi(pe) > 0 && !h->pers_plans.empty()) { h->pers = 0; return NSFRB_OK; }
+    if (std::atoi(pe) > 0) {
+      const bool stag = std::strchr(pe, 's') != nullptr;
+      for (size_t i = 0; i < h->pers_plans.size(); ++i)
+        if (h->pers_plans[i].stagger == stag) { h->pers = (int)i; return NSFRB_OK; }
+    }
   const char* env = std::getenv("NSFRB_AUTOTUNE");
   if ((ks.size() == 1 && h->pers_plans.empty()) || (env && std::atoi(env) == 0)) return NSFRB_OK;
   int bucket = 0;
   while ((1 << bucket) < h->n_pix) ++bucket;
   TuneKey key{h->C, c.n_sub, c.n_time, c.n_dm, bucket > 13 ? 13 : bucket, c.store_dtype, h->widths, {}};
-  for (const PersistentPlan& pp : h->pers_plans) key.pers_nw.push_back(pp.NW);
+  for (const PersistentPlan& pp : h->pers_plans) key.pers.push_back(2 * pp.NW + (pp.stagger ? 1 : 0));
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
       for (size_t i = 0; i < ks.size(); ++i)
         if (ks[i].PIX == it->second.pix && ks[i].NW == it->second.nw) choose(i);
-      choose_pers(it->second.pers_nw);
+      choose_pers(it->second.pers);
       return NSFRB_OK;
     }
   }
@@ -908,7 +920,7 @@ static nsfrb_status autotune(nsfrb_search* h, const std::vector<KernelClass>& ks
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune_cache[key] = {h->pix, h->nw, h->pers >= 0 ? h->pers_plans[(size_t)h->pers].NW : 0};
+  g_tune_cache[key] = {h->pix, h->nw, h->pers};
   return NSFRB_OK;
 }
 
@@ -1098,7 +1110,7 @@ extern "C" nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* i
   info[5] = pe ? 1 : 0;
   info[6] = pe ? pp->n_buf : 0;
   info[7] = pe ? (int32_t)h->pers_grids[(size_t)h->pers] : 0;
-  info[8] = 0;
+  info[8] = pe && pp->stagger ? 1 : 0;
   return NSFRB_OK;
 }
 
