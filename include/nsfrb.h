@@ -194,10 +194,8 @@ nsfrb_status nsfrb_stage_times_get(nsfrb_search* h, float* ms3);
  * workgroup, info[4] threads per workgroup, info[5] 1 if the persistent kernel
  * (one pixel per workgroup at a time, next pixel's rows loaded during the
  * search of the current one) was chosen, else 0; for it, info[6] LDS pixel
- * buffers and info[7] workgroups (0 otherwise); info[8] is 1 if that kernel is
- * the staggered form (the upper half of its waves searches the last DM
- * round's boxcars of a pixel at the start of the next one), else 0. `info`
- * holds 9 values. */
+ * buffers and info[7] workgroups (0 otherwise); info[8] is 0. `info` holds 9
+ * values. */
 nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* info);
 
 /* ---------------------------------------------------------- multi-timescale
@@ -315,13 +313,13 @@ nsfrb_status nsfrb_psf_reduce(const nsfrb_candidate* cands, int32_t n, const flo
  * share the DM trials, widths, store dtype, normalisation, layout, input
  * dtype and device; nx, ny, n_sub, n_time and frequencies may differ.
  * nsfrb_batch_run enqueues the statistics of every cube, then one persistent
- * search launch per kernel class (cubes whose tuned plans share the samples per
- * lane and pixels per workgroup; each launch's workgroups stride over the work
- * items of its cubes, with a grid sized to that kernel's occupancy), then the
- * candidates of every cube. The sequence is captured once as a hipGraph and
- * replayed while the cube pointers stay the same.
- * Results are bitwise equal to nsfrb_batch_run_separate, which runs the same
- * kernel body with one plain launch per cube. */
+ * search launch per kernel class (the cubes with the same samples per lane;
+ * each launch's workgroups walk the pixels of its cubes, with a grid sized to
+ * that kernel's occupancy), then the candidates of every cube. The sequence is
+ * captured once as a hipGraph and replayed while the cube pointers stay the
+ * same. Results are bitwise equal to nsfrb_batch_run_separate, which launches
+ * each cube's own tuned search kernel (compiled and tuned on its first call).
+ * Cube pointers must be aligned to the sample size (INVALID_ARG otherwise). */
 typedef struct nsfrb_batch nsfrb_batch;
 
 nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int32_t n_cubes, nsfrb_batch** out);

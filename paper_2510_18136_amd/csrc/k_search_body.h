@@ -403,25 +403,85 @@ __device__ __forceinline__ void stage_rows_async(const CubeDesc& cd, int p, ST* 
     }
   }
 }
-// Rows of pixel p into buf with ordinary loads and LDS stores (any alignment;
-// complete when the caller's barrier has passed).
+// 16-bit rows whose start is not dword-aligned (odd n_t, or a cube 2 bytes
+// past a dword boundary). Row s of pixel p goes to LDS index off_s + t, off_s
+// the parity of its first sample's position (row_offset), so that the global
+// and LDS dword boundaries coincide and the row is copied as the whole dwords
+// that cover it, with 4-byte global-to-LDS loads. The dword before the row
+// (off_s = 1) puts the previous row's last sample at index 0, never read; the
+// dword after it (n_t + off_s odd) puts the next row's first sample at index
+// n_t + off_s, which must read -inf: fix_row_ends rewrites it once the copies
+// have landed, and the tails start after it (row_tail). The cube's first and
+// last rows are copied with ordinary loads, so no copy reads outside the cube.
+__device__ __forceinline__ int row_parity(const CubeDesc& cd, int p) {       // off_s of row 0 of pixel p
+  return (int)((((unsigned long long)cd.z >> 1) + (unsigned long long)p * cd.n_sub * cd.n_t) & 1ull);
+}
+__device__ __forceinline__ int row_offset(int par, int s, int n_t) { return (par + s * n_t) & 1; }
+__device__ __forceinline__ int row_tail(int n_t, int off) { return n_t + off + ((n_t + off) & 1); }
+
 template <int NW>
-__device__ __forceinline__ void stage_rows_sync(const CubeDesc& cd, int p, ST* buf) {
-  const int n_sub = cd.n_sub, n_t = cd.n_t, rs = cd.rs;
-  const ST* zp = cd.z + (size_t)p * n_sub * n_t;
-  for (int k = tid_x(); k < n_sub * n_t; k += 64 * NW) {
-    const int s = k / n_t;
-    buf[s * rs + (k - s * n_t)] = zp[k];
+__device__ __forceinline__ void stage_rows_par(const CubeDesc& cd, int p, ST* buf, int wv, int l) {
+  static_assert(sizeof(ST) == 2, "only 16-bit rows can start between dwords");
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  const int rs = cd.rs, n_sub = cd.n_sub, n_t = cd.n_t;
+  const int par = row_parity(cd, p);
+  const int per_row = ((n_t + 2) / 2 + 63) / 64;          // instructions per row (at most n_t/2 + 1 dwords)
+  const unsigned char* zb = reinterpret_cast<const unsigned char*>(cd.z);
+  const long long row0 = (long long)p * n_sub, last_row = (long long)cd.n_pix * n_sub - 1;
+  for (int i = wv; i < n_sub * per_row; i += NW) {
+    const int s = i / per_row, piece = i - s * per_row;
+    const int off = row_offset(par, s, n_t);
+    const long long gr = row0 + s;
+    if ((gr == 0 && off) || (gr == last_row && ((n_t + off) & 1))) continue;   // an edge row, below
+    const int j = piece * 64 + l;                          // dword of the row
+    if (j < (n_t + off + 1) / 2) {
+      const unsigned char* g = zb + (gr * n_t - off) * 2 + 4 * (long long)j;
+      unsigned char* d = reinterpret_cast<unsigned char*>(buf + (size_t)s * rs) + (size_t)piece * 256;
+      __builtin_amdgcn_global_load_lds(g, (lds_ptr)d, 4, 0, 0);
+    }
+  }
+  // the cube's first row (if it starts between dwords) and last row (if a
+  // dword would run past it), sample by sample
+  for (int e = 0; e < 2; ++e) {
+    const int s = e == 0 ? 0 : n_sub - 1;
+    const long long gr = row0 + s;
+    const int off = row_offset(par, s, n_t);
+    if (!((e == 0 && gr == 0 && off) || (e == 1 && gr == last_row && ((n_t + off) & 1)))) continue;
+    const ST* src = cd.z + gr * n_t;
+    for (int t = tid_x(); t < n_t; t += 64 * NW) buf[(size_t)s * rs + off + t] = src[t];
+  }
+}
+// -inf where a row's last dword put the next row's first sample, written by
+// the wave that copied that dword once its copies have landed (after its own
+// s_waitcnt, before the barrier that publishes the rows); lane s looks after
+// row s (n_sub <= 64).
+template <int NW>
+__device__ __forceinline__ void fix_row_ends(const CubeDesc& cd, int p, ST* buf, int wv, int l) {
+  const int par = row_parity(cd, p), n_t = cd.n_t;
+  const int per_row = ((n_t + 2) / 2 + 63) / 64;          // the pieces of stage_rows_par
+  const int s = l, off = row_offset(par, s, n_t);
+  if (s < cd.n_sub && ((n_t + off) & 1) && (s * per_row + per_row - 1) % NW == wv)
+    buf[(size_t)s * cd.rs + n_t + off] = from_f32<ST>(kNegInf);
+}
+// -inf tails of a tile of parity-placed rows.
+template <int NW>
+__device__ __forceinline__ void fill_tails_par(ST* buf, const CubeDesc& cd, int p) {
+  const ST neg = from_f32<ST>(kNegInf);
+  const int par = row_parity(cd, p), n_t = cd.n_t, rs = cd.rs;
+  const int span = rs - n_t;                                // each row's tail is at most this long
+  for (int k = tid_x(); k < cd.n_sub * span; k += 64 * NW) {
+    const int s = k / span, u = row_tail(n_t, row_offset(par, s, n_t)) + (k - s * span);
+    if (u < rs) buf[(size_t)s * rs + u] = neg;
   }
 }
 // The copy a cube's rows allow (the batch passes it per cube): global-to-LDS
-// loads of 16 or 4 bytes per lane, else ordinary loads (16-bit samples in rows
-// of an odd length).
+// loads of 16 or 4 bytes per lane for rows of whole 16-byte vectors or dwords,
+// else (dma_w 2: 16-bit rows starting between dwords) parity-placed rows.
 template <int NW>
 __device__ __forceinline__ void stage_rows_w(const CubeDesc& cd, int p, ST* buf, int wv, int l) {
   if (cd.dma_w == 16) stage_rows_async<NW, 16>(cd, p, buf, wv, l);
   else if (cd.dma_w == 4) stage_rows_async<NW, 4>(cd, p, buf, wv, l);
-  else stage_rows_sync<NW>(cd, p, buf);
+  else if constexpr (sizeof(ST) == 2) stage_rows_par<NW>(cd, p, buf, wv, l);
 }
 
 // Between requesting a pixel's rows and waiting for them, a wave issues no
@@ -465,9 +525,10 @@ __device__ __forceinline__ void fill_tails(ST* buf, int n_sub, int n_t, int rs) 
 // registers): waves past the last trial repeat it (writing the same values
 // twice), and a trial with no valid sample is searched with zero delays (its
 // row of `delays` holds zeros) and then reported as -inf / -1.
-template <int C, int NW, class Release>
+template <int C, int NW, bool PAR = false, class Release>
 __device__ __forceinline__ void search_pixel_dms(const CubeDesc& cd, const int* delays, const int* dmaxv,
-                                                 const ST* zl, Reporter& rep, int wv, int l, Release&& release) {
+                                                 const ST* zl, Reporter& rep, int wv, int l, Release&& release,
+                                                 int par = 0) {
   const int n_dm = cd.n_dm, n_t = cd.n_t, n_sub = cd.n_sub, rs = cd.rs;
   const int n_rounds = (n_dm + NW - 1) / NW;
   for (int rd = 0; rd < n_rounds; ++rd) {
@@ -477,7 +538,8 @@ __device__ __forceinline__ void search_pixel_dms(const CubeDesc& cd, const int* 
       float cur[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) cur[c] = 0.f;
-      for (int s = 0; s < n_sub; ++s) add_row<C>(cur, zl + s * rs, ld_const(dd + s), l);
+      for (int s = 0; s < n_sub; ++s)    // (PAR: rows placed at their parity offset, see stage_rows_par)
+        add_row<C>(cur, zl + s * rs, ld_const(dd + s) + (PAR ? row_offset(par, s, n_t) : 0), l);
       if (pass == NSFRB_NPASS - 1 && rd == n_rounds - 1) release();
       nsfrb_chain<C>(pass, cur, rep);
     }
@@ -586,114 +648,6 @@ __device__ __forceinline__ void search_persistent(const CubeDesc& cd, const int*
   __builtin_amdgcn_s_waitcnt(0);
 }
 
-// Staggered persistent form (one chain pass per DM round): as search_persistent,
-// but the waves come in two halves half a step apart. All waves of a workgroup
-// start a pixel together; without the stagger they all de-disperse at once
-// (bound by LDS bandwidth, the VALU half idle) and then all run chains (bound
-// by the VALU, the LDS idle). Here every wave runs the same steps, one
-// de-dispersion and one boxcar chain each, but the early half de-disperses a
-// DM and then searches it while the late half first searches the DM it
-// de-dispersed in its previous step (for the first step of a pixel, the last
-// DM of the previous pixel) and then de-disperses the next: at any time one
-// half reads rows while the other runs a chain. The series in flight stays in
-// the same registers (`cur`) from de-dispersion to chain, so the register
-// budget is the per-DM kernel's. A pixel's best is complete only after the late
-// half's first step of the next pixel, so it is reduced one barrier later
-// (double-buffered `red`).
-template <int C, int NW, int NBUF>
-__device__ __forceinline__ void search_persistent_staggered(const CubeDesc& cd, const int* __restrict__ delays,
-                                                            const int* __restrict__ dmaxv) {
-  static_assert(NSFRB_NPASS == 1, "a deferred chain needs the de-dispersed series of a single pass");
-  extern __shared__ unsigned char lds_raw[];
-  __shared__ Best red[2][NW];
-  const int wv = __builtin_amdgcn_readfirstlane(tid_x() / kWave);
-  const int l = lane_id();
-  const bool late = wv >= NW / 2;
-  const int n_dm = cd.n_dm, n_t = cd.n_t, n_sub = cd.n_sub, rs = cd.rs;
-  const int n_rounds = (n_dm + NW - 1) / NW;
-  const int tile = n_sub * rs;
-  ST* bufs = reinterpret_cast<ST*>(lds_raw);
-  for (int b = 0; b < NBUF; ++b) fill_tails<NW>(bufs + b * tile, n_sub, n_t, rs);
-  const float norm_l = lane_norm(cd, l);
-  auto reduce_best = [&](int slot, int q) {      // thread 0: pixel q's best from the waves' bests
-    Best b = red[slot][0];
-    for (int w = 1; w < NW; ++w)
-      if (better(red[slot][w].s, red[slot][w].d, red[slot][w].w, b)) b = red[slot][w];
-    const bool ok = b.s > kNegInf;
-    cd.best_s[q] = ok ? b.s : kNegInf;
-    cd.best_d[q] = ok ? b.d : -1;
-    cd.best_w[q] = ok ? b.w : -1;
-    cd.best_t[q] = ok ? b.t : -1;
-  };
-  float cur[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) cur[c] = 0.f;
-  int cur_p = cd.n_pix, cur_d = 0;               // what cur holds (a late wave's series in flight)
-  int it = 0, p_prev = -1;
-  Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, 0, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0, norm_l};
-  auto dedisperse = [&](const ST* zl, int p, int step, int it, long long i_next) {
-    const int d = min(step * NW + wv, n_dm - 1);
-    const int* dd = delays + (size_t)d * n_sub;
-#pragma unroll
-    for (int c = 0; c < C; ++c) cur[c] = 0.f;
-    for (int s = 0; s < n_sub; ++s) add_row<C>(cur, zl + s * rs, ld_const(dd + s), l);
-    cur_p = p;
-    cur_d = d;
-    if (step == n_rounds - 1) {
-      // every wave has read this pixel's rows for the last time, and the late
-      // half has reported the previous pixel: its best is complete
-      __syncthreads();
-      if (it > 0 && tid_x() == 0) reduce_best((it - 1) & 1, p_prev);
-      if (NBUF == 1 && i_next >= 0) stage_rows_async<NW>(cd, (int)i_next, bufs, wv, l);
-    }
-  };
-  auto search = [&]() {                          // the boxcar chain of cur, reported for (cur_p, cur_d)
-    rep.p = cur_p;
-    nsfrb_chain<C>(0, cur, rep);
-    const bool searched = ld_const(dmaxv + cur_d) < n_t;
-    rep.d = cur_d;
-    rep.snr_lane = searched ? rep.snr_lane : kNegInf;
-    rep.toa_lane = searched ? rep.toa_lane : -1;
-    rep.flush();
-  };
-  const ItemWalk r = xcd_walk<NW>(cd.n_pix);
-  long long k = r.k0, i = r.item(k);
-  if (i < r.n) stage_rows_async<NW>(cd, (int)i, bufs, wv, l);
-  for (; i < r.n; ++it) {
-    const int p = (int)i;
-    k += r.step;
-    const long long i_next = r.item(k);
-    const ST* zl = bufs + (NBUF == 2 ? (it & 1) * tile : 0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (NBUF == 2 && i_next < r.n) stage_rows_async<NW>(cd, (int)i_next, bufs + ((it + 1) & 1) * tile, wv, l);
-    for (int step = 0; step < n_rounds; ++step) {
-      if (!late) dedisperse(zl, p, step, it, NBUF == 1 && i_next < r.n ? i_next : -1);
-      search();
-      if (late && step == 0) {                   // the late half's part of the previous pixel is done
-        if (l == 0 && p_prev >= 0) red[(it - 1) & 1][wv] = rep.best;
-        rep.best = Best{kNegInf, -1, -1, -1};
-      }
-      if (late) dedisperse(zl, p, step, it, NBUF == 1 && i_next < r.n ? i_next : -1);
-    }
-    if (!late) {                                 // the early half's part of this pixel is done
-      if (l == 0) red[it & 1][wv] = rep.best;
-      rep.best = Best{kNegInf, -1, -1, -1};
-    }
-    p_prev = p;
-    i = i_next;
-  }
-  if (p_prev >= 0) {                             // the late half's last series, then the last pixel's best
-    if (late) {
-      search();
-      if (l == 0) red[(it - 1) & 1][wv] = rep.best;
-    }
-    __syncthreads();
-    if (tid_x() == 0) reduce_best((it - 1) & 1, p_prev);
-  }
-  __builtin_amdgcn_s_waitcnt(0);
-}
-
 // Persistent batch: the work items of the cubes of one kernel class (PIX
 // consecutive pixels of one cube each; a cube's last item may run past its
 // pixels), concatenated in cube order (descs[c].item_begin), walked as in
@@ -725,8 +679,10 @@ __device__ __forceinline__ void search_batch_persistent(const CubeDesc* __restri
     const int p0 = (int)(i - cd.item_begin) * PIX;
 #pragma unroll
     for (int k = 0; k < PIX; ++k) {
-      fill_tails<NW>(buf + k * tile_stride, cd.n_sub, cd.n_t, cd.rs);
-      stage_rows_w<NW>(cd, min(p0 + k, cd.n_pix - 1), buf + k * tile_stride, wv, l);
+      const int pk = min(p0 + k, cd.n_pix - 1);
+      if (sizeof(ST) == 2 && cd.dma_w == 2) fill_tails_par<NW>(buf + k * tile_stride, cd, pk);
+      else fill_tails<NW>(buf + k * tile_stride, cd.n_sub, cd.n_t, cd.rs);
+      stage_rows_w<NW>(cd, pk, buf + k * tile_stride, wv, l);
     }
   };
   const ItemWalk r = xcd_walk<NW>(n_items);
@@ -741,16 +697,21 @@ __device__ __forceinline__ void search_batch_persistent(const CubeDesc* __restri
     const int c_next = i_next < r.n ? cube_of(i_next, c) : c;
     ST* buf = bufs + (NBUF == 2 ? (it & 1) * buf_stride : 0);
     __builtin_amdgcn_s_waitcnt(0);
+    if (sizeof(ST) == 2 && cd.dma_w == 2)      // parity-placed rows: restore the -inf after each row
+#pragma unroll
+      for (int k2 = 0; k2 < PIX; ++k2)
+        fix_row_ends<NW>(cd, min(p0 + k2, cd.n_pix - 1), buf + k2 * tile_stride, wv, l);
     __syncthreads();
     if (NBUF == 2 && i_next < r.n) stage(c_next, i_next, bufs + ((it + 1) & 1) * buf_stride);
     Reporter rep{CubeOut{cd.norms, cd.snr_max, cd.toa, cd.n_pix}, p0 + slot, 0, Best{kNegInf, -1, -1, -1}, 0.f, 0,
                  lane_norm(cd, l)};
-    search_pixel_dms<C, WPP>(cd, cd.delays, cd.dmax, buf + slot * tile_stride, rep, wq, l, [&]() {
+    const int par = (sizeof(ST) == 2 && cd.dma_w == 2) ? row_parity(cd, min(p0 + slot, cd.n_pix - 1)) : 0;
+    search_pixel_dms<C, WPP, true>(cd, cd.delays, cd.dmax, buf + slot * tile_stride, rep, wq, l, [&]() {
       if (NBUF == 1) {
         __syncthreads();   // no wave reads the rows of this item again
         if (i_next < r.n) stage(c_next, i_next, bufs);
       }
-    });
+    }, par);
     write_best<NW, PIX>(cd, p0, rep.best, red, wv, l);
     c = c_next;
     i = i_next;

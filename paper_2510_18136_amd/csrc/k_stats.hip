@@ -58,7 +58,7 @@ template <int V> struct StatShape {
 constexpr double kMadToSigma = 1.482602218505602;
 
 struct SeriesCtx {
-  uint32_t* hist;   // 256 bins (this wave)
+  uint32_t* hist;   // 256 bins (this wave), and a discard bin 256
   double* list;     // 64 candidates (this wave)
   int n_t;
 };
@@ -228,11 +228,12 @@ __device__ __forceinline__ int select_values(const Key& key, const Val& val, int
     cx.hist[4 * l + 0] = 0; cx.hist[4 * l + 1] = 0; cx.hist[4 * l + 2] = 0; cx.hist[4 * l + 3] = 0;
     wave_lds_sync();
     for_each_key<V>(key, [&](int, float v) {
-      if (v >= lo && v <= hi) {
-        int b = (int)((v - lo) * scale);
-        b = b > 255 ? 255 : b;
-        atomicAdd(&cx.hist[b], 1u);
-      }
+      // keys outside [lo, hi] (and NaN padding) go to bin 256, which is never
+      // read: no branch per key
+      int b = (int)((v - lo) * scale);
+      b = b > 255 ? 255 : b;
+      b = (v >= lo && v <= hi) ? b : 256;
+      atomicAdd(&cx.hist[b], 1u);
     });
     wave_lds_sync();
     const uint32_t h0 = cx.hist[4 * l], h1 = cx.hist[4 * l + 1], h2 = cx.hist[4 * l + 2], h3 = cx.hist[4 * l + 3];
@@ -594,7 +595,7 @@ __attribute__((amdgpu_waves_per_eu(StatShape<V>::kMinWavesPerEU))) void k_stats_
   // samples are conflict-free anyway
   constexpr int RS = 64 * V + 64 / kStatTilePix;
   __shared__ float series[kStatWaves * RS];
-  __shared__ uint32_t hist_all[kStatWaves][256];
+  __shared__ uint32_t hist_all[kStatWaves][260];   // 256 bins, bin 256 takes keys outside the range
   __shared__ double list_all[kStatWaves][64];
 
   // Workgroups are dealt to the 8 XCDs round-robin; remap so that each XCD

@@ -299,7 +299,6 @@ static const char* store_type_name(int store) {
 // A persistent kernel to instantiate: samples per lane, waves, LDS buffers.
 struct PersistentKernel {
   int C, NW, n_buf;
-  bool stagger;                          // late half of the waves defers its last chain (one chain pass only)
 };
 // A persistent batch kernel: samples per lane, waves, LDS buffers, pixels per item.
 struct BatchKernel {
@@ -323,10 +322,9 @@ static std::string gen_source(int store, int nw, int npass, const std::string& c
       << "(nsfrb::CubeDesc cd) { search_cube<" << k.C << ", " << k.PIX << ", " << k.NW << ">(cd); }\n";
   for (const auto& k : persistent)
     o << "extern \"C\" __global__ __launch_bounds__(" << 64 * k.NW << ") void nsfrb_persistent_c" << k.C << "_w"
-      << k.NW << "_b" << k.n_buf << (k.stagger ? "_s" : "")
-      << "(nsfrb::CubeDesc cd, const int* __restrict__ delays, const int* __restrict__ dmax) { nsfrb::"
-      << (k.stagger ? "search_persistent_staggered<" : "search_persistent<") << k.C << ", " << k.NW << ", "
-      << k.n_buf << ">(cd, delays, dmax); }\n";
+      << k.NW << "_b" << k.n_buf
+      << "(nsfrb::CubeDesc cd, const int* __restrict__ delays, const int* __restrict__ dmax) { "
+         "nsfrb::search_persistent<" << k.C << ", " << k.NW << ", " << k.n_buf << ">(cd, delays, dmax); }\n";
   // one persistent kernel per class of the batch
   for (size_t i = 0; i < batch.size(); ++i)
     o << "extern \"C\" __global__ __launch_bounds__(" << 64 * batch[i].NW << ") void nsfrb_batch_kernel_" << i
@@ -434,7 +432,6 @@ static std::vector<KernelClass> plan_candidates(int C, int n_dm, int n_sub, int 
 // multiple of 16, pitch padded to 16 bytes), in one or two LDS buffers.
 struct PersistentPlan {
   int NW = 16, rs = 0, n_buf = 1;
-  bool stagger = false;                  // search_persistent_staggered
   size_t lds = 0;
 };
 
@@ -473,8 +470,7 @@ static std::vector<PersistentPlan> persistent_candidates(int n_dm, int n_sub, in
 }
 
 static std::string persistent_kernel_name(int C, const PersistentPlan& pp) {
-  return "nsfrb_persistent_c" + std::to_string(C) + "_w" + std::to_string(pp.NW) + "_b" + std::to_string(pp.n_buf) +
-         (pp.stagger ? "_s" : "");
+  return "nsfrb_persistent_c" + std::to_string(C) + "_w" + std::to_string(pp.NW) + "_b" + std::to_string(pp.n_buf);
 }
 
 // Host-only entry: generate (and optionally compile) the specialised search
@@ -502,8 +498,7 @@ extern "C" int nsfrb_debug_plan_source(const nsfrb_search_config* cfg, char* out
   std::vector<BatchKernel> bks;          // batch kernels of the same shapes, one and two pixels per item
   for (const PersistentPlan& pp : persistent_candidates(cfg->n_dm, cfg->n_sub, cfg->n_time, C, dmax_search,
                                                         cfg->store_dtype)) {
-    pks.push_back({C, pp.NW, pp.n_buf, false});
-    if (npass == 1) pks.push_back({C, pp.NW, pp.n_buf, true});
+    pks.push_back({C, pp.NW, pp.n_buf});
     bks.push_back({C, pp.NW, pp.n_buf, 1});
     bks.push_back({C, pp.NW, 1, 2});
   }
@@ -613,15 +608,9 @@ static nsfrb_status plan_kernels(nsfrb_search* h) {
     if (pers_only != 0)
       for (const PersistentPlan& pp : persistent_candidates(cfg->n_dm, cfg->n_sub, cfg->n_time, h->C, h->dmax_search,
                                                             cfg->store_dtype))
-        if (pers_only < 0 || pp.NW == pers_only) {
-          pps.push_back(pp);
-          if (npass == 1) {              // the staggered form keeps one pass's series across pixels
-            pps.push_back(pp);
-            pps.back().stagger = true;
-          }
-        }
+        if (pers_only < 0 || pp.NW == pers_only) pps.push_back(pp);
     std::vector<PersistentKernel> pks;
-    for (const PersistentPlan& pp : pps) pks.push_back({h->C, pp.NW, pp.n_buf, pp.stagger});
+    for (const PersistentPlan& pp : pps) pks.push_back({h->C, pp.NW, pp.n_buf});
     h->source = gen_source(cfg->store_dtype, cfg->n_width, npass, chain, h->cands, {}, pks);
     st = load_module(h->device, h->source, &h->mod);
     if (st != NSFRB_OK) return st;
@@ -823,7 +812,7 @@ static nsfrb_status launch_search(const nsfrb_search* h, const void* z, hipStrea
 struct TuneKey {
   int C, n_sub, n_t, n_dm, n_pix_bucket, store;
   std::vector<int32_t> widths;
-  std::vector<int32_t> pers;    // the persistent candidates: 2 NW + (staggered)
+  std::vector<int32_t> pers;    // the persistent candidates' waves
   bool operator<(const TuneKey& o) const {
     return std::tie(C, n_sub, n_t, n_dm, n_pix_bucket, store, widths, pers) <
            std::tie(o.C, o.n_sub, o.n_t, o.n_dm, o.n_pix_bucket, o.store, o.widths, o.pers);
@@ -851,19 +840,15 @@ static nsfrb_status autotune(nsfrb_search* h, const std::vector<KernelClass>& ks
       for (size_t i = 0; i < ks.size(); ++i)
         if (ks[i].PIX == pp && ks[i].NW == ww) { choose(i); return NSFRB_OK; }
   }
-  // NSFRB_PERSISTENT=NW (NW > 0) keeps that persistent kernel, "NWs" its staggered form (for studies)
+  // NSFRB_PERSISTENT=NW (NW > 0) keeps that persistent kernel (for studies)
   if (const char* pe = std::getenv("NSFRB_PERSISTENT"))
-    if (std::atoi(pe) > 0) {
-      const bool stag = std::strchr(pe, 's') != nullptr;
-      for (size_t i = 0; i < h->pers_plans.size(); ++i)
-        if (h->pers_plans[i].stagger == stag) { h->pers = (int)i; return NSFRB_OK; }
-    }
+    if (std::atoi(pe) > 0 && !h->pers_plans.empty()) { h->pers = 0; return NSFRB_OK; }
   const char* env = std::getenv("NSFRB_AUTOTUNE");
   if ((ks.size() == 1 && h->pers_plans.empty()) || (env && std::atoi(env) == 0)) return NSFRB_OK;
   int bucket = 0;
   while ((1 << bucket) < h->n_pix) ++bucket;
   TuneKey key{h->C, c.n_sub, c.n_time, c.n_dm, bucket > 13 ? 13 : bucket, c.store_dtype, h->widths, {}};
-  for (const PersistentPlan& pp : h->pers_plans) key.pers.push_back(2 * pp.NW + (pp.stagger ? 1 : 0));
+  for (const PersistentPlan& pp : h->pers_plans) key.pers.push_back(pp.NW);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -1110,7 +1095,7 @@ extern "C" nsfrb_status nsfrb_search_plan_info(const nsfrb_search* h, int32_t* i
   info[5] = pe ? 1 : 0;
   info[6] = pe ? pp->n_buf : 0;
   info[7] = pe ? (int32_t)h->pers_grids[(size_t)h->pers] : 0;
-  info[8] = pe && pp->stagger ? 1 : 0;
+  info[8] = 0;
   return NSFRB_OK;
 }
 
@@ -1368,9 +1353,10 @@ extern "C" nsfrb_status nsfrb_batch_run(nsfrb_batch* b, const void* const* d_cub
       d.z = h->cfg.layout == NSFRB_LAYOUT_TSP ? h->d_z : d_cubes[i];
       // row copy the cube allows: global-to-LDS loads of 16 (4) bytes per lane
       // for rows of whole 16-byte (4-byte) vectors from a 16-byte (4-byte)
-      // aligned cube, else ordinary loads (2)
-      const size_t row_bytes = (size_t)h->cfg.n_time * dtype_size(h->cfg.store_dtype);
+      // aligned cube, else (2) 16-bit rows placed at their dword parity
+      const size_t es = dtype_size(h->cfg.store_dtype), row_bytes = (size_t)h->cfg.n_time * es;
       const uintptr_t zp = reinterpret_cast<uintptr_t>(d.z);
+      if (zp % es != 0) return fail(NSFRB_ERR_INVALID_ARG, "cube " + std::to_string(i) + " is not aligned to its sample size");
       d.dma_w = (row_bytes % 16 == 0 && zp % 16 == 0) ? 16 : (row_bytes % 4 == 0 && zp % 4 == 0) ? 4 : 2;
     }
     HIP_TRY(hipMemcpy(b->d_descs, b->descs.data(), b->descs.size() * sizeof(CubeDescHost), hipMemcpyHostToDevice));

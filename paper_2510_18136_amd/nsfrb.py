@@ -525,7 +525,7 @@ class Search:
         check(lib().nsfrb_search_plan_info(self.h, _ptr(out, ctypes.c_int32)))
         return dict(samples_per_lane=int(out[0]), pixels_per_workgroup=int(out[1]), row_len=int(out[2]),
                     lds_bytes=int(out[3]), threads_per_workgroup=int(out[4]), persistent=bool(out[5]),
-                    lds_buffers=int(out[6]), workgroups=int(out[7]), staggered=bool(out[8]))
+                    lds_buffers=int(out[6]), workgroups=int(out[7]))
 
 
 class Batch:

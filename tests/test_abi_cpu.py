@@ -129,6 +129,25 @@ def test_search_kernel_compiles_for_gfx950(L, store):
     c1.plan_source(compile=True)
 
 
+def test_plans_compile_in_a_process_that_imported_torch(L):
+    """In a process that has imported the PyTorch wheel, hipRTC compiles with
+    the wheel's bundled compiler (an older one), which once crashed on a batch
+    kernel the system compiler accepted. Compile the plans (search, persistent
+    and batch kernels) there, in a child process."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import torch, numpy as np\n"
+        "from paper_2510_18136_amd import nsfrb, synth\n"
+        "for store in ('f32', 'f16', 'bf16'):\n"
+        "    nsfrb.SearchConfig(32, 32, 64, synth.C1_FREQS, np.linspace(0, 1000, 8), [1, 2, 3, 5, 16, 63],\n"
+        "                       store_dtype=store).plan_source(compile=True)\n"
+        "print('compiled')\n" % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0 and "compiled" in r.stdout, (r.returncode, r.stderr[-2000:])
+
+
 def test_many_open_accumulators_split_into_passes(L):
     c = nsfrb.SearchConfig(4, 4, 1024, [1.3, 1.4], [0.0], [1023, 1021, 1019, 1017, 1, 64, 5])
     src = c.plan_source(compile=True)

@@ -1,11 +1,10 @@
 """GPU tests of every search kernel form, each forced in turn (needs an MI355X).
 
-The per-DM kernel, the persistent kernel (one pixel per workgroup at a time,
-the next pixel's rows fetched during the current one) and its staggered form
-(half the waves search the last DM of a pixel at the start of the next) must
-give maps, per-pixel best trials and candidates bitwise equal to each other:
-they sum in the same order and differ only in which wave does what, when. The
-per-DM results are held to the oracle. Shapes cover one, two and three DM
+The per-DM kernel and the persistent kernel (one pixel per workgroup at a time,
+the next pixel's rows fetched during the current one), with 16 and with 8
+waves, must give maps, per-pixel best trials and candidates bitwise equal to
+each other: they sum in the same order and differ only in which wave does
+what, when. The per-DM results are held to the oracle. Shapes cover one, two and three DM
 rounds per wave, pixel counts that are not multiples of the 32-pixel chunks,
 one and two LDS buffers, and FP32 and FP16 stores.
 """
@@ -43,15 +42,14 @@ def pulsed_cube(nt, npix, seed):
 def forms(monkeypatch, cfg, cube):
     """Results of each kernel form the plan offers, keyed by form."""
     out = {}
-    for mode, want in (("0", (False, False)), ("16", (True, False)), ("16s", (True, True)),
-                       ("8", (True, False)), ("8s", (True, True))):
+    for mode in ("0", "16", "8"):
         monkeypatch.setenv("NSFRB_PERSISTENT", mode)
         with nsfrb.Search(cfg) as s:
             info = s.plan_info()
-        if (info["persistent"], info["staggered"]) != want:
+        if info["persistent"] != (mode != "0"):
             continue                     # this shape has no such kernel (e.g. 16 waves with fewer DMs)
         if mode != "0":
-            assert info["threads_per_workgroup"] == 64 * int(mode.rstrip("s"))
+            assert info["threads_per_workgroup"] == 64 * int(mode)
         print(f"[gpu] form {mode}: {info}", flush=True)
         out[mode] = run_gpu(cube, cfg)
     monkeypatch.delenv("NSFRB_PERSISTENT")
@@ -69,7 +67,7 @@ def test_every_kernel_form_gives_the_same_results(monkeypatch, n_dm, nx, ny, nt,
     cfg = nsfrb.SearchConfig(nx, ny, nt, FREQS, np.linspace(0, 4000, n_dm), widths, store_dtype=store,
                              snr_threshold=6.0, max_candidates=64)
     res = forms(monkeypatch, cfg, cube)
-    assert "0" in res and any(m.endswith("s") for m in res), sorted(res)
+    assert "0" in res and len(res) >= 2, sorted(res)
     ref = res["0"]
     for mode, g in res.items():
         assert np.array_equal(g["snr"], ref["snr"], equal_nan=True), mode
