@@ -1144,13 +1144,16 @@ static void batch_release(nsfrb_batch* b) {
   delete b;
 }
 
-// Pixels per batch work item (tile: one pixel's LDS rows in bytes). One by
-// default: on the 64-cube benchmark batch (8 DM trials) two and four pixels
-// per item measured 146 and 168 ms against 123 ms. NSFRB_BATCH_PIX = 2 or 4
-// asks for more (fewer barriers per pixel when a pixel's trials are few);
+// Pixels per batch work item (tile: one pixel's LDS rows in bytes): two for
+// short series (C <= 18 samples per lane), whose items are short enough that
+// the per-item wait for rows and the barriers show; one otherwise, where a
+// second pixel's tile would cost a workgroup per CU. Measured per class on the
+// 64-cube benchmark batch: two pixels saved 4-10% on C = 6..18 and cost
+// 28-50% on C = 22..30. NSFRB_BATCH_PIX = 1, 2 or 4 sets the count (studies);
 // never more than fit in LDS.
-static int batch_pixels_per_item(int nw, int env, size_t tile) {
-  int pix = (env == 2 || env == 4) ? std::min(env, nw) : 1;
+static int batch_pixels_per_item(int C, int nw, int env, size_t tile) {
+  int pix = (env == 1 || env == 2 || env == 4) ? env : (C <= 18 ? 2 : 1);
+  pix = std::min(pix, nw);
   while (pix > 1 && (size_t)pix * tile > kLdsBudget) pix >>= 1;
   return pix;
 }
@@ -1208,7 +1211,7 @@ extern "C" nsfrb_status nsfrb_batch_create(const nsfrb_search_config* cfgs, int3
     for (size_t i = 0; i < b->cubes.size(); ++i)
       if (cls_of[i] == (int)c)
         tile1 = std::max(tile1, b->cubes[i]->cfg.n_sub * ((b->cubes[i]->rs + align - 1) / align * align));
-    bc.k.PIX = batch_pixels_per_item(nw_b, pix_env, (size_t)tile1 * sz);
+    bc.k.PIX = batch_pixels_per_item(bc.k.C, nw_b, pix_env, (size_t)tile1 * sz);
     bc.first_desc = (int)b->descs.size();
     for (size_t i = 0; i < b->cubes.size(); ++i) {
       if (cls_of[i] != (int)c) continue;
