@@ -57,6 +57,19 @@ template <int V> struct StatShape {
 };
 constexpr double kMadToSigma = 1.482602218505602;
 
+typedef const __attribute__((address_space(1))) char* gptr;   // global memory
+// One input sample at a global address, as FP32.
+template <typename InT> __device__ __forceinline__ float load_global_f32(gptr a) {
+  if constexpr (sizeof(InT) == 4) {
+    return __uint_as_float(*(const __attribute__((address_space(1))) uint32_t*)a);
+  } else {
+    const uint16_t bits = *(const __attribute__((address_space(1))) uint16_t*)a;
+    InT v;
+    __builtin_memcpy(&v, &bits, 2);
+    return to_f32(v);
+  }
+}
+
 struct SeriesCtx {
   uint32_t* hist;   // 256 bins (this wave), and a discard bin 256
   double* list;     // 64 candidates (this wave)
@@ -553,28 +566,44 @@ __device__ __forceinline__ void process_series(const float* xs, int p, int s, in
   asm volatile("" : "+v"(med));
   ST* zrow = z + ((size_t)p * n_sub + s) * n_t;
   int nbad_samples = 0;
+  if (mode == NORM_PIXEL_SUBBAND && usable && fast_div && n_t == 64 * V) {
+    // the usual case, with no per-sample branch: every register holds a
+    // sample, every sample is finite (a non-finite one makes the series
+    // unusable) and the quotient is Markstein's
 #pragma unroll
-  for (int j = 0; j < V; ++j) {
-    const int t = 64 * j + l;
-    if (t < n_t) {
-      float zf;
-      const float xj = x(j);
-      const bool fin = __builtin_isfinite(xj);
-      if (mode == NORM_NONE) {
-        zf = fin ? xj : 0.0f;
-        nbad_samples += !fin;
-      } else if (!usable) {
-        zf = 0.0f;
-      } else if (mode == NORM_EXTERNAL && !fin) {
-        zf = 0.0f;
-        nbad_samples += 1;
-      } else {
-        const double a = (double)xj - med;
-        zf = (float)(fast_div ? div_markstein(a, sig, r) : a / sig);
-      }
-      zrow[t] = from_f32<ST>(zf);
+    for (int j = 0; j < V; ++j) {
+      const double a = (double)x(j) - med;
+      float zf = (float)div_markstein(a, sig, r);
+      // z is rounded to FP32 first and then to the store type; without the
+      // barrier the compiler merges the two roundings into one from FP64
+      asm("" : "+v"(zf));
+      zrow[64 * j + l] = from_f32<ST>(zf);
+      if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bound the live FP64 temporaries
     }
-    if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bound the live FP64 temporaries
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int t = 64 * j + l;
+      if (t < n_t) {
+        float zf;
+        const float xj = x(j);
+        const bool fin = __builtin_isfinite(xj);
+        if (mode == NORM_NONE) {
+          zf = fin ? xj : 0.0f;
+          nbad_samples += !fin;
+        } else if (!usable) {
+          zf = 0.0f;
+        } else if (mode == NORM_EXTERNAL && !fin) {
+          zf = 0.0f;
+          nbad_samples += 1;
+        } else {
+          const double a = (double)xj - med;
+          zf = (float)(fast_div ? div_markstein(a, sig, r) : a / sig);
+        }
+        zrow[t] = from_f32<ST>(zf);
+      }
+      if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
   }
   if (mode == NORM_NONE || mode == NORM_EXTERNAL) nflag += wave_sum(nbad_samples);
   if (l == 0 && nflag) atomicAdd(flag_count, (unsigned long long)nflag);
@@ -619,29 +648,62 @@ __attribute__((amdgpu_waves_per_eu(StatShape<V>::kMinWavesPerEU))) void k_stats_
   constexpr int kPer = 64 * V / kRowStep;                           // loads per thread
   const int c_ld = threadIdx.x % kStatTilePix;
   const bool pix_ok = p0 + c_ld < n_pix;
-  const InT* src = x + (size_t)s * n_pix + (pix_ok ? p0 + c_ld : 0);
   const int r0 = threadIdx.x / kStatTilePix;
   float stage[kPer];
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int t = q * kRowStep + r0;
-    const bool ok = pix_ok && t < n_t;
-    int tr = t + t_start;                          // ring order: oldest sample first
-    tr -= tr >= n_t ? n_t : 0;
-    const float v = to_f32(src[(size_t)(ok ? tr : 0) * plane]);
-    stage[q] = ok ? v : __builtin_nanf("");
-  }
   // the thread's samples all belong to series c_ld: its partial extremes and
   // non-finite flag go to that series' (not yet used) histogram slots, where
   // the series' wave combines the kRowStep partials (saves a pass over the row)
   float tmin = __builtin_inff(), tmax = -__builtin_inff();
   bool tbad = false;
+  if (t_start == 0 && n_t == 64 * V && (size_t)kRowStep * plane * sizeof(InT) < 0x80000000u) {
+    // Plain cube filling every register: the time rows of chunk q start at a
+    // workgroup-uniform address, and each thread adds the same 32-bit offset
+    // (its pixel and its row within the chunk) to every one of them. Threads
+    // of pixels past n_pix read pixel p0 instead (their rows belong to no
+    // processed series). fma(v, 0, acc) stays 0 unless some v is infinite or
+    // NaN.
+    const char* tile = (const char*)(x + (size_t)s * n_pix + p0);
+    const uint32_t voff = (uint32_t)(((pix_ok ? c_ld : 0) + (size_t)r0 * plane) * sizeof(InT));
+    // The row address is held in scalar registers and stepped by one add per
+    // chunk, so each load adds voff to it (left to itself the compiler folds
+    // the row step into a 64-bit vector multiply-add per load).
+    gptr row = (gptr)tile;
+    const size_t step = (size_t)kRowStep * plane * sizeof(InT);
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int t = q * kRowStep + r0;
-    tbad |= (t < n_t) && !__builtin_isfinite(stage[q]);
-    tmin = fminf(tmin, stage[q]);
-    tmax = fmaxf(tmax, stage[q]);
+    for (int q = 0; q < kPer; ++q) {
+      stage[q] = load_global_f32<InT>(row + voff);
+      row += step;
+      asm("" : "+s"(row));
+    }
+    float nf = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      nf = __builtin_fmaf(stage[q], 0.0f, nf);
+      tmin = fminf(tmin, stage[q]);
+      tmax = fmaxf(tmax, stage[q]);
+    }
+    tbad = nf != 0.0f;
+  } else {
+    // Ring of the last n_t samples (read oldest first), a series shorter than
+    // the registers, or a plane too large for 32-bit offsets. Rows beyond n_t
+    // and pixels beyond n_pix load a valid address and become NaN.
+    const InT* src = x + (size_t)s * n_pix + (pix_ok ? p0 + c_ld : 0);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = q * kRowStep + r0;
+      const bool ok = pix_ok && t < n_t;
+      int tr = t + t_start;                        // ring order: oldest sample first
+      tr -= tr >= n_t ? n_t : 0;
+      stage[q] = to_f32(src[(size_t)(ok ? tr : 0) * plane]);
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = q * kRowStep + r0;
+      stage[q] = pix_ok && t < n_t ? stage[q] : __builtin_nanf("");
+      tbad |= (t < n_t) && !__builtin_isfinite(stage[q]);
+      tmin = fminf(tmin, stage[q]);
+      tmax = fmaxf(tmax, stage[q]);
+    }
   }
   float* my_row = series + c_ld * RS + r0;
 #pragma unroll
