@@ -146,11 +146,15 @@ __device__ __forceinline__ double lane_read_d(double v, int src) {
   return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
 
-// Ascending bitonic sort of one value per lane across the wave.
-__device__ __forceinline__ double wave_sort_asc(double v) {
+// Ascending bitonic sort of one value per lane over lanes [0, K), K the
+// smallest power of two >= n (at least 2; n <= 64): the merge stages of
+// blocks wider than K are skipped, so a few candidates cost a few stages.
+// Lanes from K up are left in an unspecified order.
+__device__ __forceinline__ double wave_sort_asc(double v, int n) {
   const int l = lane_id();
 #pragma unroll
   for (int k = 2; k <= kWave; k <<= 1) {
+    if (k > 2 && n <= (k >> 1)) break;             // uniform: lanes [0, k/2) already sorted
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
       double o = lane_read_d(v, l ^ j);

@@ -15,8 +15,9 @@
 // time-contiguous to the search layout [p][s][t].
 //
 // Exact selection: an order statistic of FP32 keys is found by adaptive
-// histogramming over [lo, hi] into 256 equal bins (bin = floor((v - lo) *
-// scale), a monotone map, so rank bookkeeping is exact whatever the rounding),
+// histogramming over [lo, hi] into 256 equal bins (bin = (v - lo) * scale
+// rounded down, a monotone map, so rank bookkeeping is exact whatever the
+// rounding),
 // keeping only the bin that holds the wanted rank, until <= 64 candidates
 // remain; those are sorted across the wave. Each round shrinks the range
 // strictly, so the loop ends; a range too narrow to bin falls back to stepping
@@ -182,7 +183,7 @@ __device__ __forceinline__ Sel select_kth_f32(const Key& key, int k, const Serie
       wave_lds_sync();
       double c = (l < (int)cnt) ? cx.list[l] : __builtin_inf();
       wave_lds_sync();
-      c = wave_sort_asc(c);
+      c = wave_sort_asc(c, (int)cnt);
       const float kv = (float)readlane_d(c, krem);
       // rank among equal keys: krem minus the candidates below it
       const int below = popc64(ballot(l < (int)cnt && c < (double)kv));
@@ -231,23 +232,37 @@ __device__ __forceinline__ Sel select_kth_f32(const Key& key, int k, const Serie
 // histogram of the whole range [lo, hi].
 template <int V, class Key, class Val>
 __device__ __forceinline__ int select_values(const Key& key, const Val& val, int k, bool want_second, float lo,
-                                              float hi, const SeriesCtx& cx, double& first, double& second) {
+                                              float hi, bool all_in, const SeriesCtx& cx, double& first,
+                                              double& second) {
   const int l = lane_id();
   int krem = k;                                    // rank among keys in [lo, hi]
   for (int iter = 0; iter < 48; ++iter) {
     if (!(lo < hi)) return 0;
     const float scale = 256.0f / (hi - lo);
     if (!(scale > 0.0f && scale < 1e30f)) return 0;
+    // bin(v) = trunc(fma(v, scale, -lo scale)) clamped to [0, 255]: monotone
+    // in v (the rounding of -lo scale shifts every bin edge alike)
+    const float off = -lo * scale;
+    auto bin_of = [&](float v) {
+      const int b = (int)__builtin_fmaf(v, scale, off);
+      return min(max(b, 0), 255);
+    };
+    // keys known to lie in [lo, hi]: the first round when every register holds
+    // a finite key and [lo, hi] spans them all
+    const bool in_range = all_in && iter == 0;
     cx.hist[4 * l + 0] = 0; cx.hist[4 * l + 1] = 0; cx.hist[4 * l + 2] = 0; cx.hist[4 * l + 3] = 0;
     wave_lds_sync();
-    for_each_key<V>(key, [&](int, float v) {
-      // keys outside [lo, hi] (and NaN padding) go to bin 256, which is never
-      // read: no branch per key
-      int b = (int)((v - lo) * scale);
-      b = b > 255 ? 255 : b;
-      b = (v >= lo && v <= hi) ? b : 256;
-      atomicAdd(&cx.hist[b], 1u);
-    });
+    if (in_range) {
+      for_each_key<V>(key, [&](int, float v) { atomicAdd(&cx.hist[bin_of(v)], 1u); });
+      asm volatile("");                             // keeps this loop from being merged with the checked one
+    } else {
+      for_each_key<V>(key, [&](int, float v) {
+        // keys outside [lo, hi] (and NaN padding) go to bin 256, which is never
+        // read: no branch per key
+        const int b = (v >= lo && v <= hi) ? bin_of(v) : 256;
+        atomicAdd(&cx.hist[b], 1u);
+      });
+    }
     wave_lds_sync();
     const uint32_t h0 = cx.hist[4 * l], h1 = cx.hist[4 * l + 1], h2 = cx.hist[4 * l + 2], h3 = cx.hist[4 * l + 3];
     const uint32_t s4 = h0 + h1 + h2 + h3;
@@ -270,12 +285,7 @@ __device__ __forceinline__ int select_values(const Key& key, const Val& val, int
     if (cnt <= 64) {
       int base = 0;
       for_each_key<V>(key, [&](int j, float v) {
-        bool mem = false;
-        if (v >= lo && v <= hi) {
-          int b = (int)((v - lo) * scale);
-          b = b > 255 ? 255 : b;
-          mem = (b == B);
-        }
+        const bool mem = (in_range || (v >= lo && v <= hi)) && bin_of(v) == B;
         const uint64_t mm = ballot(mem);
         if (mem) cx.list[base + lanes_below(mm)] = val(j);
         base += popc64(mm);
@@ -283,7 +293,7 @@ __device__ __forceinline__ int select_values(const Key& key, const Val& val, int
       wave_lds_sync();
       double c = (l < (int)cnt) ? cx.list[l] : __builtin_inf();
       wave_lds_sync();
-      c = wave_sort_asc(c);
+      c = wave_sort_asc(c, (int)cnt);
       first = readlane_d(c, krem);
       if (!want_second) return iter + 1;
       if (krem + 1 < (int)cnt) {
@@ -304,11 +314,7 @@ __device__ __forceinline__ int select_values(const Key& key, const Val& val, int
 #pragma unroll
     for (int j = 0; j < V; ++j) {
       const float v = key(j);
-      if (v >= lo && v <= hi) {
-        int b = (int)((v - lo) * scale);
-        b = b > 255 ? 255 : b;
-        if (b == B) { nlo = fminf(nlo, v); nhi = fmaxf(nhi, v); }
-      }
+      if ((v >= lo && v <= hi) && bin_of(v) == B) { nlo = fminf(nlo, v); nhi = fmaxf(nhi, v); }
     }
     lo = wave_min_f(nlo);
     hi = wave_max_f(nhi);
@@ -390,7 +396,7 @@ __device__ __forceinline__ bool mad_from_bracket(const LdsSeries& x, double med,
   wave_lds_sync();
   double c = (l < base) ? cx.list[l] : __builtin_inf();
   wave_lds_sync();
-  c = wave_sort_asc(c);
+  c = wave_sort_asc(c, base);
   const double a = readlane_d(c, k - below);
   mad = even ? (a + readlane_d(c, k - below + 1)) * 0.5 : a;
   return true;
@@ -417,7 +423,7 @@ __device__ __forceinline__ void resolve_ties(const Key& key, float kv, int rank,
     wave_lds_sync();
     double c = (l < base) ? cx.list[l] : __builtin_inf();
     wave_lds_sync();
-    c = wave_sort_asc(c);
+    c = wave_sort_asc(c, base);
     first = readlane_d(c, rank);
     second = (rank + 1 < base) ? readlane_d(c, rank + 1) : __builtin_inf();
     return;
@@ -492,6 +498,17 @@ __device__ __forceinline__ double median_via_keys(const Key& key, const Val& val
   return (a + b) * 0.5;
 }
 
+// A z sample written with the non-temporal hint: the z cube is streamed out
+// once (the search reads it back much later), so its lines should not displace
+// the raw cube's, which neighbouring tiles still read.
+template <typename ST> __device__ __forceinline__ void store_z(ST* p, float zf) {
+  const ST v = from_f32<ST>(zf);
+  if constexpr (sizeof(ST) == 4)
+    __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, v), (uint32_t*)p);
+  else
+    __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, v), (uint16_t*)p);
+}
+
 __device__ __forceinline__ double div_markstein(double a, double b, double r) {
   const double q0 = a * r;
   const double e = __builtin_fma(-q0, b, a);
@@ -525,7 +542,8 @@ __device__ __forceinline__ void process_series(const float* xs, int p, int s, in
       const bool even = (n_t & 1) == 0;
       double a = 0.0, b = 0.0;
       auto vx = [&](int j) { return (double)x(j); };
-      const int rounds = select_values<V>(x, vx, k1, even, xmin, xmax, cx, a, b);
+      const bool full = n_t == 64 * V;              // no NaN padding
+      const int rounds = select_values<V>(x, vx, k1, even, xmin, xmax, full, cx, a, b);
       if (rounds)
         med = even ? (a + b) * 0.5 : a;
       else
@@ -542,7 +560,7 @@ __device__ __forceinline__ void process_series(const float* xs, int p, int s, in
       const float dhi = fmaxf((float)fabs((double)xmax - med), (float)fabs((double)xmin - med));
       double mad;
       if (rounds == 1 && mad_from_bracket<V>(x, mv, k1, even, xmin, 256.0f / (xmax - xmin), dhi, cx, mad)) {
-      } else if (select_values<V>(DistKeys{x, mk}, vd, k1, even, 0.0f, dhi, cx, a, b)) {
+      } else if (select_values<V>(DistKeys{x, mk}, vd, k1, even, 0.0f, dhi, full, cx, a, b)) {
         mad = even ? (a + b) * 0.5 : a;
       } else {
         mad = median_via_keys<false, V>(DistKeys{x, mk}, vd, cx);
@@ -577,7 +595,7 @@ __device__ __forceinline__ void process_series(const float* xs, int p, int s, in
       // z is rounded to FP32 first and then to the store type; without the
       // barrier the compiler merges the two roundings into one from FP64
       asm("" : "+v"(zf));
-      zrow[64 * j + l] = from_f32<ST>(zf);
+      store_z<ST>(zrow + 64 * j + l, zf);
       if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bound the live FP64 temporaries
     }
   } else {
@@ -600,7 +618,7 @@ __device__ __forceinline__ void process_series(const float* xs, int p, int s, in
           const double a = (double)xj - med;
           zf = (float)(fast_div ? div_markstein(a, sig, r) : a / sig);
         }
-        zrow[t] = from_f32<ST>(zf);
+        store_z<ST>(zrow + t, zf);
       }
       if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
