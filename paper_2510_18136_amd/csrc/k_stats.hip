@@ -598,6 +598,22 @@ __device__ __forceinline__ void process_series(const float* xs, int p, int s, in
       store_z<ST>(zrow + 64 * j + l, zf);
       if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // bound the live FP64 temporaries
     }
+  } else if (mode == NORM_PIXEL_SUBBAND && usable && fast_div) {
+    // the same with registers left over: four quotients are formed before
+    // their stores, which only lanes holding a sample make
+#pragma unroll
+    for (int j0 = 0; j0 < V; j0 += 4) {
+      float zf[4];
+#pragma unroll
+      for (int b = 0; b < 4 && j0 + b < V; ++b) {
+        zf[b] = (float)div_markstein((double)x(j0 + b) - med, sig, r);
+        asm("" : "+v"(zf[b]));
+      }
+#pragma unroll
+      for (int b = 0; b < 4 && j0 + b < V; ++b)
+        if (64 * (j0 + b) + l < n_t) store_z<ST>(zrow + 64 * (j0 + b) + l, zf[b]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   } else {
 #pragma unroll
     for (int j = 0; j < V; ++j) {
@@ -701,10 +717,38 @@ __attribute__((amdgpu_waves_per_eu(StatShape<V>::kMinWavesPerEU))) void k_stats_
       tmax = fmaxf(tmax, stage[q]);
     }
     tbad = nf != 0.0f;
+  } else if (t_start == 0 && (size_t)kRowStep * plane * sizeof(InT) < 0x80000000u) {
+    // Plain cube of a length that leaves registers over: the same loads, and
+    // a thread whose row of a chunk lies past n_t reads the chunk's first row
+    // (or, for a chunk wholly past n_t, the cube's) and keeps NaN instead.
+    // Every value loaded is one of the series' own samples, so the
+    // non-finite check can take them all.
+    const char* tile = (const char*)(x + (size_t)s * n_pix + p0);
+    const uint32_t coff = (uint32_t)((pix_ok ? c_ld : 0) * sizeof(InT));
+    const uint32_t voff = coff + (uint32_t)((size_t)r0 * plane * sizeof(InT));
+    gptr row = (gptr)tile;
+    const size_t step = (size_t)kRowStep * plane * sizeof(InT);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      gptr rq = q * kRowStep < n_t ? row : (gptr)tile;
+      asm("" : "+s"(rq));
+      stage[q] = load_global_f32<InT>(rq + (q * kRowStep + r0 < n_t ? voff : coff));
+      row += step;
+      asm("" : "+s"(row));
+    }
+    float nf = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      nf = __builtin_fmaf(stage[q], 0.0f, nf);
+      stage[q] = q * kRowStep + r0 < n_t ? stage[q] : __builtin_nanf("");
+      tmin = fminf(tmin, stage[q]);
+      tmax = fmaxf(tmax, stage[q]);
+    }
+    tbad = nf != 0.0f;
   } else {
-    // Ring of the last n_t samples (read oldest first), a series shorter than
-    // the registers, or a plane too large for 32-bit offsets. Rows beyond n_t
-    // and pixels beyond n_pix load a valid address and become NaN.
+    // Ring of the last n_t samples (read oldest first), or a plane too large
+    // for 32-bit offsets. Rows beyond n_t and pixels beyond n_pix load a valid
+    // address and become NaN.
     const InT* src = x + (size_t)s * n_pix + (pix_ok ? p0 + c_ld : 0);
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
