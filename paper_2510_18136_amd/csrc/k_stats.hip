@@ -72,7 +72,7 @@ template <typename InT> __device__ __forceinline__ float load_global_f32(gptr a)
 }
 
 struct SeriesCtx {
-  uint32_t* hist;   // 256 bins (this wave), and a discard bin 256
+  uint32_t* hist;   // 256 bins (this wave)
   double* list;     // 64 candidates (this wave)
   int n_t;
 };
@@ -256,11 +256,11 @@ __device__ __forceinline__ int select_values(const Key& key, const Val& val, int
       for_each_key<V>(key, [&](int, float v) { atomicAdd(&cx.hist[bin_of(v)], 1u); });
       asm volatile("");                             // keeps this loop from being merged with the checked one
     } else {
+      // keys outside [lo, hi] (and NaN padding) are masked off; sending them
+      // all to one discard bin instead would make up to 64 lanes of an atomic
+      // hit the same address, which the LDS serialises
       for_each_key<V>(key, [&](int, float v) {
-        // keys outside [lo, hi] (and NaN padding) go to bin 256, which is never
-        // read: no branch per key
-        const int b = (v >= lo && v <= hi) ? bin_of(v) : 256;
-        atomicAdd(&cx.hist[b], 1u);
+        if (v >= lo && v <= hi) atomicAdd(&cx.hist[bin_of(v)], 1u);
       });
     }
     wave_lds_sync();
@@ -658,7 +658,7 @@ __attribute__((amdgpu_waves_per_eu(StatShape<V>::kMinWavesPerEU))) void k_stats_
   // samples are conflict-free anyway
   constexpr int RS = 64 * V + 64 / kStatTilePix;
   __shared__ float series[kStatWaves * RS];
-  __shared__ uint32_t hist_all[kStatWaves][260];   // 256 bins, bin 256 takes keys outside the range
+  __shared__ uint32_t hist_all[kStatWaves][256];
   __shared__ double list_all[kStatWaves][64];
 
   // Workgroups are dealt to the 8 XCDs round-robin; remap so that each XCD
